@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the one-loop Symanzik gauge action and force (arXiv:1808.02281, Sec. II).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package. It shares no code with the GPU library
+(``paper_1808_02281_amd``) and neither imports the other.
+
+Pinned by ``tests/test_oracle_*.py`` against closed forms, exact symmetries, a numpy
+brute-force enumeration, finite differences of the action and leapfrog invariants.
+"""
+from .oracle import (  # noqa: F401
+    coeffs,
+    loop_table,
+    action,
+    force,
+    force_links,
+    staple_sums,
+    local_action,
+    su3_exp,
+    kinetic,
+    leapfrog,
+    num_threads,
+    gell_mann,
+    lie_derivative,
+)

@@ -1,0 +1,186 @@
+"""ctypes wrapper over ``libsymoracle.so`` (FP64 C oracle). Test infrastructure only.
+
+Arrays are numpy complex128 in the canonical array-of-structures lexicographic layout
+``(Lt, Lz, Ly, Lx, 4, 3, 3)``: site index ``((t*Lz + z)*Ly + y)*Lx + x``, direction
+``mu = 0..3`` for ``x, y, z, t``. ``L`` is always given as ``(Lx, Ly, Lz, Lt)``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsymoracle.so")
+_lib = None
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+_c_int64_p = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build
+
+        build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.orc_coeffs.argtypes = [ctypes.c_double, _c_double_p, _c_double_p]
+    lib.orc_coeffs.restype = ctypes.c_int
+    lib.orc_loop_table.argtypes = [_c_int32_p, _c_int32_p, _c_int32_p]
+    lib.orc_loop_table.restype = ctypes.c_int
+    lib.orc_action.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, _c_double_p]
+    lib.orc_action.restype = ctypes.c_double
+    lib.orc_force.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, vp]
+    lib.orc_force.restype = None
+    lib.orc_force_links.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, ctypes.c_int64,
+                                    _c_int64_p, _c_int32_p, vp]
+    lib.orc_force_links.restype = None
+    lib.orc_staple_sums.argtypes = [_c_int32_p, vp, vp]
+    lib.orc_staple_sums.restype = None
+    lib.orc_local_action.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, ctypes.c_int64,
+                                     ctypes.c_int32]
+    lib.orc_local_action.restype = ctypes.c_double
+    lib.orc_su3_exp.argtypes = [ctypes.c_int64, vp, vp]
+    lib.orc_su3_exp.restype = None
+    lib.orc_kinetic.argtypes = [_c_int32_p, vp]
+    lib.orc_kinetic.restype = ctypes.c_double
+    lib.orc_leapfrog.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, vp, ctypes.c_double,
+                                 ctypes.c_int32, _c_double_p]
+    lib.orc_leapfrog.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dims(L):
+    a = (ctypes.c_int32 * 4)(*[int(v) for v in L])
+    return a
+
+
+def _cvec(c):
+    return (ctypes.c_double * 3)(*[float(v) for v in c])
+
+
+def _field(U, L):
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    Lx, Ly, Lz, Lt = L
+    if U.shape != (Lt, Lz, Ly, Lx, 4, 3, 3):
+        raise ValueError(f"field shape {U.shape} does not match L={tuple(L)}")
+    return U
+
+
+def coeffs(u0):
+    """(c_plaq, c_rect, c_cube), alpha_s from u0 (eq. 18_3_27_30 and the alpha_s formula)."""
+    c = (ctypes.c_double * 3)()
+    a = ctypes.c_double()
+    if _load().orc_coeffs(float(u0), c, ctypes.byref(a)) != 0:
+        raise ValueError("u0 must be positive and finite")
+    return np.array(list(c)), a.value
+
+
+def loop_table():
+    """The 34 loops: (len[34], cls[34], dirs[34,6]) with signed directions +-1..+-4."""
+    ln = (ctypes.c_int32 * 34)()
+    cl = (ctypes.c_int32 * 34)()
+    d = (ctypes.c_int32 * (34 * 6))()
+    n = _load().orc_loop_table(ln, cl, d)
+    return np.array(ln[:n]), np.array(cl[:n]), np.array(d[:]).reshape(34, 6)[:n]
+
+
+def action(U, L, c, beta):
+    """S_G and W = (W_plaq, W_rect, W_cube) = per-class sums of Re tr P_n (eq. 18_6_4_1)."""
+    U = _field(U, L)
+    W = (ctypes.c_double * 3)()
+    S = _load().orc_action(_dims(L), _cvec(c), float(beta), U.ctypes.data, W)
+    return S, np.array(list(W))
+
+
+def force(U, L, c, beta):
+    """G = (beta/6)(U t)_TA on every link, shape like U (force algorithm of Sec. II)."""
+    U = _field(U, L)
+    G = np.empty_like(U)
+    _load().orc_force(_dims(L), _cvec(c), float(beta), U.ctypes.data, G.ctypes.data)
+    return G
+
+
+def force_links(U, L, c, beta, sites, mus):
+    """G on a list of links given by lexicographic site index and direction."""
+    U = _field(U, L)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    G = np.empty((len(sites), 3, 3), dtype=np.complex128)
+    _load().orc_force_links(_dims(L), _cvec(c), float(beta), U.ctypes.data, len(sites),
+                            sites.ctypes.data_as(_c_int64_p), mus.ctypes.data_as(_c_int32_p),
+                            G.ctypes.data)
+    return G
+
+
+def staple_sums(U, L):
+    """Unweighted per-class staple sums t[cls] for every link: shape U.shape[:-2] + (3, 3, 3)."""
+    U = _field(U, L)
+    out = np.empty(U.shape[:-2] + (3, 3, 3), dtype=np.complex128)
+    _load().orc_staple_sums(_dims(L), U.ctypes.data, out.ctypes.data)
+    return out
+
+
+def local_action(U, L, c, beta, site, mu):
+    """The part of S_G carried by the loops through link (site, mu)."""
+    U = _field(U, L)
+    return _load().orc_local_action(_dims(L), _cvec(c), float(beta), U.ctypes.data, int(site), int(mu))
+
+
+def su3_exp(X):
+    """exp(X) for a stack of 3x3 complex matrices (Taylor series, scaling and squaring)."""
+    X = np.ascontiguousarray(X, dtype=np.complex128)
+    out = np.empty_like(X)
+    n = X.size // 9
+    _load().orc_su3_exp(n, X.ctypes.data, out.ctypes.data)
+    return out
+
+
+def kinetic(P, L):
+    """sum over links of -tr(Pi^2) for antihermitian momenta Pi."""
+    P = _field(P, L)
+    return _load().orc_kinetic(_dims(L), P.ctypes.data)
+
+
+def leapfrog(U, P, L, c, beta, dt, nsteps):
+    """Leapfrog trajectory; returns (U_end, P_end, H_start, H_end). Inputs are not modified."""
+    U = _field(U, L).copy()
+    P = _field(P, L).copy()
+    H = (ctypes.c_double * 2)()
+    rc = _load().orc_leapfrog(_dims(L), _cvec(c), float(beta), U.ctypes.data, P.ctypes.data,
+                              float(dt), int(nsteps), H)
+    if rc != 0:
+        raise MemoryError("oracle leapfrog could not allocate its force buffer")
+    return U, P, H[0], H[1]
+
+
+def num_threads():
+    return _load().orc_num_threads()
+
+
+def gell_mann():
+    """T_a = lambda_a / 2, the su(3) generators with tr(T_a T_b) = delta_ab / 2 (eq. 18_1_29_3_0)."""
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1], lam[1][1, 0] = -1j, 1j
+    lam[2][0, 0], lam[2][1, 1] = 1, -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2], lam[4][2, 0] = -1j, 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2], lam[6][2, 1] = -1j, 1j
+    lam[7][0, 0] = lam[7][1, 1] = 1 / np.sqrt(3)
+    lam[7][2, 2] = -2 / np.sqrt(3)
+    return lam / 2
+
+
+def lie_derivative(G):
+    """dS/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U (from the force identity of Sec. II)."""
+    T = gell_mann()
+    return np.real(-2j * np.einsum("aij,...ji->...a", T, G))
