@@ -1,0 +1,275 @@
+"""Benchmark of the Symanzik gauge force on one MI355X.
+
+Workload: the 32^3x64 periodic lattice with near-thermal links U = exp(i 0.25 r.T)
+(r ~ N(0,1), seed 2), u0 = 0.8677, beta = 3. One step is one force pass over all
+8,388,608 links with the action fused (coefficients, staple sums, TA force, FP64
+action reduction), on fields resident in HBM in the even-odd SoA layout. The
+headline is FP32 link products with FP64 action; the FP64 form is timed beside it.
+
+Prints one JSON line (metric, value = link-forces/s, roofline of the dominant kernel,
+CPU-oracle baseline, FP64 comparison, leapfrog step timing).
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py --copy-calibration      # plain copy kernel for rocprof byte counters
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "link-forces/sec + % HBM/VALU roofline, Symanzik force 32^3x64, FP32 vs FP64"
+WORKLOAD = "thermal_32x32x32x64"
+
+# Work per link-force (flop; FMA = 2). See the design notes for the derivation.
+FLOP_PAPER = 36770          # the paper's algorithm: 180 staple products, sums, U t, TA
+FLOP_STAPLES = 2376         # factored pass 1: 6 plaquette staples x 2 products
+FLOP_FACTORED = 11494       # factored pass 2: 51 products + sums, traces, TA
+FLOP_DIRECT = 36940         # direct kernel: 181 products + sums, traces, TA
+# Minimum HBM bytes per link of each kernel (read once / write once), per real size r.
+BYTES_STAPLES = lambda r: (18 + 6 * 18) * r              # read U, write 6 staples
+BYTES_FACTORED = lambda r: (18 + 6 * 18 + 18) * r        # read U and own staples, write G
+BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
+
+PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts packed FMA)
+PEAK_F32_NONPACKED = 78.6e12               # 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_factored_f32_32x32x32x64_traffic.json")
+KERNEL_SOURCES = ["force_factored.hip", "su3.hpp", "lattice.hpp", "kernels.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_02281_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counters, or
+    None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_force(sym, torch, U, L, u0, beta, steps, warmup):
+    F = torch.empty_like(U)
+    for _ in range(warmup):
+        sym.force(U, L, u0, beta, with_action=True, out=F)
+    torch.cuda.synchronize()
+    sym.profile_enable(True)
+    sym.profile_collect()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    S = None
+    for _ in range(steps):
+        _, S = sym.force(U, L, u0, beta, with_action=True, out=F)
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernels = sym.profile_collect()
+    sym.profile_enable(False)
+    ms = start.elapsed_time(end) / steps
+    return ms, wall, kernels, F, float(S[0].item())
+
+
+def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
+    """The FP64 oracle's force on a random sample of links of the same workload."""
+    import numpy as np
+
+    import oracle
+
+    c, _ = oracle.coeffs(u0)
+    V = int(np.prod(L))
+    rng = np.random.default_rng(99)
+    n = 4096
+    while True:
+        sites = rng.integers(0, V, n)
+        mus = rng.integers(0, 4, n).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.force_links(U_np, L, c, beta, sites, mus)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 4 or n >= 4 * V:
+            break
+        n = min(4 * V, int(n * max(2.0, budget_s / max(dt, 1e-3) * 0.9)))
+    return {
+        "value": n / dt,
+        "unit": "link-forces/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} random links of the 32^3x64 workload, FP64, C oracle with OpenMP ({dt:.1f} s)",
+    }
+
+
+def copy_calibration(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the force would shard by domain decomposition; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    import gaugegen
+    import paper_1808_02281_amd as sym
+
+    if args.only_f32:
+        args.no_cpu_baseline = args.no_fp64 = args.no_md = True
+
+    cfg = gaugegen.CONFIGS[WORKLOAD]
+    L = cfg["L"]
+    u0, beta = gaugegen.U0, gaugegen.BETA
+    V = int(np.prod(L))
+    links = 4 * V
+    dev = torch.device("cuda:0")
+
+    log(f"generating {WORKLOAD} (eps={cfg['eps']}, seed={cfg['seed']})")
+    t0 = time.perf_counter()
+    U_np = gaugegen.near_thermal_links(L, cfg["eps"], cfg["seed"])
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+    aos = torch.from_numpy(U_np).to(dev)
+    U32 = sym.pack(aos.to(torch.complex64), L)
+    U64 = None if args.no_fp64 else sym.pack(aos, L)
+    del aos
+    torch.cuda.synchronize()
+
+    log("timing FP32 force")
+    ms32, wall32, k32, F32, S32 = time_force(sym, torch, U32, L, u0, beta, args.steps, args.warmup)
+    value = links / (ms32 * 1e-3)
+    log(f"  {ms32:.3f} ms/step, kernels {k32}")
+
+    def kernel_avg(kernels, name):
+        tot, n = kernels.get(name, (0.0, 0))
+        return tot / n if n else None
+
+    dom = "force_factored" if "force_factored" in k32 else "force_direct"
+    t_dom = kernel_avg(k32, dom) * 1e-3
+    flop_dom = FLOP_FACTORED if dom == "force_factored" else FLOP_DIRECT
+    bytes_dom = (BYTES_FACTORED if dom == "force_factored" else BYTES_DIRECT)(4)
+    alu = flop_dom * links / t_dom
+    hbm = bytes_dom * links / t_dom
+    traffic = measured_traffic() if dom == "force_factored" else None
+    roofline = {
+        "kernel": dom,
+        "bound": "alu",
+        "achieved": alu / 1e12,
+        "peak": PEAK["f32"] / 1e12,
+        "unit": "TFLOP/s",
+        "frac": alu / PEAK["f32"],
+        "traffic": traffic,
+        "flop_per_link": flop_dom,
+        "frac_of_nonpacked_fp32_peak": alu / PEAK_F32_NONPACKED,
+        "hbm_min_bytes_per_link": bytes_dom,
+        "hbm_frac_at_min_bytes": hbm / PEAK_HBM,
+        "kernel_ms": t_dom * 1e3,
+    }
+    if traffic:
+        roofline["hbm_frac_measured"] = traffic / t_dom / PEAK_HBM
+    paper_equiv = FLOP_PAPER * value
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "link-forces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "lattice": list(L), "links": links, "eps": cfg["eps"], "seed": cfg["seed"],
+                   "u0": u0, "beta": beta, "precision": "f32 link products, f64 action reduction",
+                   "algorithm": "factored" if dom == "force_factored" else "direct"},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in k32.items()},
+        "paper_equivalent": {"flop_per_link": FLOP_PAPER, "tflops": paper_equiv / 1e12,
+                             "frac_of_fp32_peak": paper_equiv / PEAK["f32"]},
+        "action_f32": S32,
+        "wall_s": wall32,
+    }
+
+    if not args.no_fp64:
+        log("timing FP64 force")
+        ms64, _, k64, F64, S64 = time_force(sym, torch, U64, L, u0, beta, args.steps, args.warmup)
+        d = (F32.to(torch.float64) - F64).reshape(4, 2, 9, -1, 2)
+        dn = torch.sqrt((d * d).sum(dim=(2, 4))).max().item()
+        rn = torch.sqrt((F64.reshape(4, 2, 9, -1, 2) ** 2).sum(dim=(2, 4))).max().item()
+        out["fp64"] = {"value": links / (ms64 * 1e-3), "ms_per_step": ms64,
+                       "kernels_ms_per_step": {k: v[0] / args.steps for k, v in k64.items()},
+                       "action": S64}
+        out["fp32_speedup_over_fp64"] = ms64 / ms32
+        out["fp32_vs_fp64"] = {"force_max_rel": dn / rn, "action_rel": abs(S32 - S64) / abs(S64)}
+        del F64
+        log(f"  {ms64:.3f} ms/step")
+
+    if not args.no_md:
+        log("timing FP32 leapfrog")
+        P = sym.pack(torch.from_numpy(gaugegen.momenta(L, 4)).to(torch.complex64).to(dev), L)
+        Um = U32.clone()
+        nst = 4
+        sym.md_leapfrog(Um, P, L, u0, beta, 0.02, 1, with_energy=False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sym.md_leapfrog(Um, P, L, u0, beta, 0.02, nst, with_energy=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["md_leapfrog"] = {"prec": "f32", "nsteps": nst, "dt": 0.02, "ms_per_step": ms / nst,
+                              "link_updates_per_s": links * nst / (ms * 1e-3)}
+        del P, Um
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(U_np, L, u0, beta)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * sym.h -- C ABI of libsym.so: the one-loop Symanzik improved gauge action, its
+ * molecular-dynamics force and a leapfrog update, on AMD Instinct MI355X (gfx950).
+ *
+ * Source of the method: D. Li, "The Calculation of Force in Lattice Quantum
+ * Chromodynamics", arXiv:1808.02281, Sec. II ("One-loop Symanzik improved action").
+ *
+ * Conventions
+ *   L = {Lx, Ly, Lz, Lt}: lattice dimensions, each even and >= 4, periodic in all four
+ *     directions; V = Lx*Ly*Lz*Lt sites, 4V links; V/2 <= 2^27.
+ *   Directions mu = 0..3 are x, y, z, t; U_{n,mu} lives on the link (n, n+mu) and
+ *     U_{n,-mu} = U^dagger_{n-mu,mu}.
+ *   prec: SYM_F32 (links, forces and momenta stored as float; products in float; every
+ *     global sum -- action, Hamiltonian -- and the exponential of the link update in
+ *     double) or SYM_F64 (everything in double).
+ *   Link-field layout ("SoA even-odd"): for site n = (x,y,z,t) let
+ *     lex = ((t*Lz + z)*Ly + y)*Lx + x, parity p = (x+y+z+t) & 1, cb = lex >> 1.
+ *     The matrix element (row r, col c) of link (n, mu) is the complex number
+ *     (re, im) at complex index ((mu*2 + p)*9 + 3*r + c) * (V/2) + cb, i.e. the buffer
+ *     is real[4][2][9][V/2][2] of float or double. Force and momentum fields use the
+ *     same layout.
+ *   Canonical layout (sym_pack / sym_unpack only): complex array-of-structures
+ *     (Lt, Lz, Ly, Lx, 4, 3, 3), row-major, float or double pairs per prec.
+ *
+ * Memory, streams, errors
+ *   Every pointer argument except c_out/alpha_s_out of sym_coeffs is device memory,
+ *   16-byte aligned, owned by the caller. The library allocates no device memory and
+ *   keeps no state besides the process-wide switches below (coefficient override,
+ *   force algorithm, kernel timing); scratch space is the caller's workspace ws of at
+ *   least sym_workspace_bytes(L, prec) bytes.
+ *   All work is enqueued on `stream` (a hipStream_t; NULL = default stream) and the
+ *   calls return without synchronising; results such as S_dev are device doubles.
+ *   Arguments are validated on the host before anything is launched; a negative
+ *   sym_status is returned and nothing is enqueued. A failed launch returns SYM_EHIP;
+ *   faults inside kernels surface at the caller's next synchronisation. Nothing throws
+ *   or aborts across this interface. Calls on different streams with different
+ *   workspaces may run concurrently.
+ */
+#ifndef SYM_H
+#define SYM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* sym_stream_t; /* hipStream_t */
+
+typedef enum {
+  SYM_OK = 0,
+  SYM_EINVAL = -1,       /* bad dimension, precision, scalar, algorithm or alignment */
+  SYM_ENULL = -2,        /* a required pointer is NULL */
+  SYM_EWORKSPACE = -3,   /* ws_bytes < sym_workspace_bytes(L, prec) */
+  SYM_EHIP = -4,         /* a HIP launch failed (e.g. no gfx950 device) */
+  SYM_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} sym_status;
+
+typedef enum { SYM_F32 = 1, SYM_F64 = 2 } sym_prec;
+
+/* Force algorithms (both compute the same G; see sym_set_force_algorithm). */
+typedef enum { SYM_ALG_AUTO = 0, SYM_ALG_DIRECT = 1, SYM_ALG_FACTORED = 2 } sym_algorithm;
+
+/*
+ * Tadpole-improved loop coefficients from u0 (Sec. II, eq. 18_3_27_30 and the line
+ * after eq. 18_6_6_3_0): alpha_s = -4 ln(u0) / 3.06839, c_out = {c_plaq, c_rect,
+ * c_cube} = {1, -(1 + 0.4805 alpha_s)/(20 u0^2), -2 * 0.03325 alpha_s / u0^2}.
+ * Host pointers; alpha_s_out may be NULL. SYM_EINVAL unless u0 > 0 and finite.
+ */
+int sym_coeffs(double u0, double c_out[3], double* alpha_s_out);
+
+/* Bytes of workspace every entry point below needs for lattice L and precision prec
+ * (0 if L or prec is invalid). */
+size_t sym_workspace_bytes(const int32_t L[4], int prec);
+
+/*
+ * S_G = beta/3 sum_n sum_P c_P [3 - Re tr P_n] over the 34 loops per site
+ * (eq. 18_6_4_1), accumulated in double. U: link field (read). S_dev: 4 device
+ * doubles, written {S_G, W_P, W_R, W_C} with W_X = sum_n sum_{P in X} Re tr P_n.
+ */
+int sym_action(const int32_t L[4], double u0, double beta, int prec, const void* U, double* S_dev, void* ws,
+               size_t ws_bytes, sym_stream_t stream);
+
+/*
+ * Gauge force of S_G on every link (Sec. II, eq. 18_7_25_2 and the algorithm after
+ * eq. 18_6_6_13): G_{k,rho} = (beta/6) (U_{k,rho} t_{k,rho})_TA, with t the c_P-weighted
+ * sum of the 48 staples of the link and TA of eq. 18_6_6_11. G is traceless and
+ * antihermitian; the paper's Hermitian force -sum_i T_i dS/domega^i is iG, and
+ * dS/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U. U: link field (read);
+ * F: output, same layout. S_dev: NULL, or 4 device doubles that receive the action as
+ * in sym_action, computed from the same staple sums (each loop of class X is seen once
+ * from each of its L_X = 4, 6, 6 links).
+ */
+int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* U, void* F, double* S_dev, void* ws,
+              size_t ws_bytes, sym_stream_t stream);
+
+/*
+ * nsteps leapfrog steps of the molecular dynamics of H = sum_links -tr(Pi^2) + S_G,
+ * with U-dot = Pi U and Pi-dot = -G (U = exp(i omega.T), dU/domega = iTU; Sec. II):
+ * per step Pi -= dt/2 G(U); U <- exp(dt Pi) U; Pi -= dt/2 G(U), consecutive half kicks
+ * merged. The exponential and U update are in double. U: links (in/out); P: momenta
+ * Pi = i sum_a p_a T_a, antihermitian (in/out). H_dev: NULL or 2 device doubles,
+ * {H before, H after}. No reunitarisation.
+ */
+int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,
+                double* H_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
+
+/* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
+int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
+int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);
+
+/*
+ * Process-wide test switch: use these three loop coefficients instead of the ones
+ * derived from u0 (e.g. {1, 0, 0} gives the Wilson plaquette action). c = NULL
+ * restores the u0 coefficients. Not meant to be flipped while calls are in flight.
+ */
+int sym_set_coeffs_override(const double c[3]);
+
+/*
+ * Process-wide choice of force algorithm: SYM_ALG_DIRECT multiplies out all 48
+ * staples of each link (181 SU(3) products per link); SYM_ALG_FACTORED first forms
+ * the 6 plaquette staples of every link and builds rectangles and cube loops from
+ * them; SYM_ALG_AUTO (default) picks the faster. SYM_EINVAL for other values.
+ */
+int sym_set_force_algorithm(int algorithm);
+
+/* Static description of a status code. */
+const char* sym_strerror(int status);
+
+/*
+ * Per-kernel timing for profiling and benchmarks. With profiling on, every kernel the
+ * library launches is bracketed by two HIP timing events recorded on the launch stream
+ * (the events are created lazily and reused; no device memory is allocated).
+ * sym_profile_collect waits for the recorded events, writes at most max_kinds entries
+ * -- kernel name (NUL-terminated, 32 bytes per entry in names), summed milliseconds and
+ * launch count -- in order of first launch, forgets them, and returns the number of
+ * entries (or a negative sym_status). Host pointers. Process-wide; not for use while
+ * other threads launch work through the library.
+ */
+int sym_profile_enable(int on);
+int sym_profile_collect(int max_kinds, char* names, double* total_ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYM_H */

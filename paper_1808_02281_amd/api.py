@@ -1,0 +1,180 @@
+"""Python binding over the C ABI (include/sym.h): argument marshalling only.
+
+Fields live on the GPU as torch tensors in the even-odd structure-of-arrays layout:
+real tensors of shape ``(4, 2, 9, V/2, 2)`` (direction, parity, matrix element,
+checkerboard site, re/im), float32 or float64. Every computation runs in the HIP
+kernels of libsym.so on the current torch stream; nothing here computes physics.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+_WS_CACHE = {}
+
+
+def prec_of(dtype):
+    if dtype == torch.float32:
+        return _lib.SYM_F32
+    if dtype == torch.float64:
+        return _lib.SYM_F64
+    raise TypeError(f"fields must be float32 or float64, got {dtype}")
+
+
+def volume(L):
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    return Lx * Ly * Lz * Lt
+
+
+def field_shape(L):
+    """Shape of a link/force/momentum field in the SoA even-odd layout."""
+    return (4, 2, 9, volume(L) // 2, 2)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_field(name, t, L):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != field_shape(L):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {field_shape(L)} for L={tuple(L)}")
+    prec_of(t.dtype)
+
+
+def coeffs(u0):
+    """(c_plaq, c_rect, c_cube), alpha_s (host computation inside the library)."""
+    c = (ctypes.c_double * 3)()
+    a = ctypes.c_double()
+    _lib.check("sym_coeffs", _lib.lib().sym_coeffs(float(u0), c, ctypes.byref(a)))
+    return [c[0], c[1], c[2]], a.value
+
+
+def workspace_bytes(L, prec):
+    return int(_lib.lib().sym_workspace_bytes(_lib.dims(L), int(prec)))
+
+
+def workspace(L, prec, device):
+    """A cached device workspace of sym_workspace_bytes(L, prec) bytes."""
+    device = torch.device(device)
+    key = (device.index, tuple(int(v) for v in L), int(prec))
+    ws = _WS_CACHE.get(key)
+    if ws is None:
+        n = workspace_bytes(L, prec)
+        if n == 0:
+            raise ValueError(f"invalid lattice {tuple(L)} or precision {prec}")
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = ws
+    return ws
+
+
+def release_workspaces():
+    _WS_CACHE.clear()
+
+
+def pack(aos, L):
+    """Canonical complex (Lt,Lz,Ly,Lx,4,3,3) CUDA tensor -> SoA even-odd real field."""
+    if not aos.is_cuda or not aos.is_contiguous():
+        raise ValueError("aos must be a contiguous CUDA tensor")
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    if tuple(aos.shape) != (Lt, Lz, Ly, Lx, 4, 3, 3):
+        raise ValueError(f"aos shape {tuple(aos.shape)} does not match L={tuple(L)}")
+    real = {torch.complex64: torch.float32, torch.complex128: torch.float64}.get(aos.dtype)
+    if real is None:
+        raise TypeError("aos must be complex64 or complex128")
+    out = torch.empty(field_shape(L), dtype=real, device=aos.device)
+    _lib.check("sym_pack", _lib.lib().sym_pack(_lib.dims(L), prec_of(real), _ptr(aos), _ptr(out), _stream(aos.device)))
+    return out
+
+
+def unpack(soa, L):
+    """SoA even-odd real field -> canonical complex (Lt,Lz,Ly,Lx,4,3,3) tensor."""
+    _check_field("soa", soa, L)
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    cdt = torch.complex64 if soa.dtype == torch.float32 else torch.complex128
+    out = torch.empty((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=cdt, device=soa.device)
+    _lib.check("sym_unpack", _lib.lib().sym_unpack(_lib.dims(L), prec_of(soa.dtype), _ptr(soa), _ptr(out),
+                                                   _stream(soa.device)))
+    return out
+
+
+def action(U, L, u0, beta):
+    """S_G and W_P, W_R, W_C as a float64 CUDA tensor of 4 (asynchronous)."""
+    _check_field("U", U, L)
+    prec = prec_of(U.dtype)
+    ws = workspace(L, prec, U.device)
+    S = torch.empty(4, dtype=torch.float64, device=U.device)
+    _lib.check("sym_action", _lib.lib().sym_action(_lib.dims(L), float(u0), float(beta), prec, _ptr(U), _ptr(S),
+                                                   _ptr(ws), ws.numel(), _stream(U.device)))
+    return S
+
+
+def force(U, L, u0, beta, with_action=False, out=None):
+    """G = (beta/6)(U t)_TA on every link; with_action also returns S as in ``action``."""
+    _check_field("U", U, L)
+    prec = prec_of(U.dtype)
+    ws = workspace(L, prec, U.device)
+    F = torch.empty_like(U) if out is None else out
+    _check_field("out", F, L)
+    S = torch.empty(4, dtype=torch.float64, device=U.device) if with_action else None
+    _lib.check("sym_force", _lib.lib().sym_force(_lib.dims(L), float(u0), float(beta), prec, _ptr(U), _ptr(F),
+                                                 _ptr(S) if S is not None else None, _ptr(ws), ws.numel(),
+                                                 _stream(U.device)))
+    return (F, S) if with_action else F
+
+
+def md_leapfrog(U, P, L, u0, beta, dt, nsteps, with_energy=True):
+    """In-place leapfrog on (U, P); returns H = [H_start, H_end] (float64 CUDA tensor)."""
+    _check_field("U", U, L)
+    _check_field("P", P, L)
+    if U.dtype != P.dtype:
+        raise TypeError("U and P must have the same dtype")
+    prec = prec_of(U.dtype)
+    ws = workspace(L, prec, U.device)
+    H = torch.empty(2, dtype=torch.float64, device=U.device) if with_energy else None
+    _lib.check("md_leapfrog", _lib.lib().md_leapfrog(_lib.dims(L), float(u0), float(beta), prec, _ptr(U), _ptr(P),
+                                                     float(dt), int(nsteps), _ptr(H) if H is not None else None,
+                                                     _ptr(ws), ws.numel(), _stream(U.device)))
+    return H
+
+
+def set_coeffs_override(c):
+    """Use loop coefficients c = (c_plaq, c_rect, c_cube) instead of u0's; None restores."""
+    if c is None:
+        return _lib.check("sym_set_coeffs_override", _lib.lib().sym_set_coeffs_override(None))
+    arr = (ctypes.c_double * 3)(*[float(v) for v in c])
+    return _lib.check("sym_set_coeffs_override", _lib.lib().sym_set_coeffs_override(arr))
+
+
+def set_force_algorithm(name):
+    """'auto' (default), 'direct' or 'factored'."""
+    return _lib.check("sym_set_force_algorithm", _lib.lib().sym_set_force_algorithm(_lib.ALGORITHMS[name]))
+
+
+def profile_enable(on=True):
+    """Bracket every library kernel launch with HIP timing events (see sym_profile_enable)."""
+    return _lib.check("sym_profile_enable", _lib.lib().sym_profile_enable(1 if on else 0))
+
+
+def profile_collect(max_kinds=32):
+    """{kernel name: (total ms, launches)} for the launches recorded since the last call."""
+    names = ctypes.create_string_buffer(32 * max_kinds)
+    ms = (ctypes.c_double * max_kinds)()
+    cnt = (ctypes.c_int32 * max_kinds)()
+    n = _lib.lib().sym_profile_collect(max_kinds, names, ms, cnt)
+    if n < 0:
+        _lib.check("sym_profile_collect", n)
+    raw = names.raw
+    out = {}
+    for k in range(n):
+        name = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
+        out[name] = (ms[k], cnt[k])
+    return out

@@ -1,0 +1,75 @@
+// Internal launch interface between the C ABI (sym_abi.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "lattice.hpp"
+
+namespace sym {
+
+constexpr int kBlock = 256;  // threads per workgroup for the per-link kernels
+
+// Coefficients of the three loop classes and beta (eq. 18_3_27_30, eq. 18_6_4_1).
+struct Coeffs {
+  double c[3];  // plaquette, rectangle, cube
+  double beta;
+};
+
+// What a force kernel does with G = (beta/6)(U t)_TA.
+enum class ForceOut { Store = 0, Kick = 1 };
+
+// Number of workgroups of a per-link launch (a multiple of 8: 4 directions x 2 parities).
+inline int link_tiles(const Geom& g) { return ((g.Vh + kBlock - 1) / kBlock) * 8; }
+
+// Each per-link force launch writes 3 doubles per workgroup: sum of Re tr(U t_X).
+// The action kernel writes 3 per workgroup too (W_X partials).
+
+// Direct force: every staple of the generated table multiplied out (Sec. II algorithm).
+template <typename T>
+hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, double* partials,
+                               const Coeffs& c, ForceOut mode, hipStream_t s);
+
+// Factored force: plaquette staples first (one pass), then rectangles and cube loops
+// assembled from them (second pass).
+// Staple buffer: 8 slots of 9 complex per link (two slots unused), see force_factored.hip.
+inline int factored_tiles(const Geom& g) { return link_tiles(g); }
+template <typename T>
+hipError_t launch_staples(const Geom& g, const T* U, T* S8, hipStream_t s);
+template <typename T>
+hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out, double kick,
+                                 double* partials, const Coeffs& c, ForceOut mode, hipStream_t s);
+
+// Action: loop products per site; W partials per workgroup.
+int action_tiles(const Geom& g);
+template <typename T>
+hipError_t launch_action(const Geom& g, const T* U, double* partials, hipStream_t s);
+
+// Final deterministic reduction of per-workgroup partials. All partials are "deficit"
+// sums of (3 - Re tr loop), three per workgroup:
+//   kind 0 (direct force): per-link sums over each class's staples (divide by 4, 6, 6);
+//   kind 1 (action kernel): per-site sums over each class's loops;
+//   kind 2 (factored force): plaquette / long-side rectangle / (c_R short-side
+//          rectangle + c_C cube) sums, see force_factored.hip.
+// launch_finish_action writes out[0..3] = S, W_P, W_R, W_C; launch_finish_hamiltonian
+// adds the kinetic partials and writes out[0] = S + kinetic.
+hipError_t launch_finish_action(const double* partials, int nparts, int kind, const Geom& g,
+                                const Coeffs& c, double* out, hipStream_t s);
+
+// Leapfrog pieces.
+template <typename T>
+hipError_t launch_kinetic(const Geom& g, const T* P, double* partials, hipStream_t s);
+hipError_t launch_finish_hamiltonian(const double* act_parts, int nact, int act_kind,
+                                     const double* kin_parts, int nkin, const Geom& g,
+                                     const Coeffs& c, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_drift(const Geom& g, T* U, const T* P, double dt, hipStream_t s);
+
+// Layout conversion between array-of-structures lexicographic complex
+// (Lt,Lz,Ly,Lx,4,3,3) and the even-odd structure-of-arrays layout.
+template <typename T>
+hipError_t launch_pack(const Geom& g, const T* aos, T* soa, hipStream_t s);
+template <typename T>
+hipError_t launch_unpack(const Geom& g, const T* soa, T* aos, hipStream_t s);
+
+}  // namespace sym

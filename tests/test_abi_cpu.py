@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+symbol of include/sym.h, computes coefficients and workspace sizes, and rejects bad
+arguments before launching anything. Pointers passed here are never dereferenced:
+each call fails validation first."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L_():
+    from paper_1808_02281_amd import _lib
+
+    try:
+        return _lib.lib()
+    except ImportError as e:
+        pytest.fail(f"libsym.so not built: {e}")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sym.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_]+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol(L_):
+    from paper_1808_02281_amd import _lib
+
+    declared = _declared_functions()
+    assert sorted(_lib.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(L_, name), name
+
+
+def test_coeffs_match_oracle(L_):
+    from paper_1808_02281_amd import api
+
+    for u0 in (0.8677, 0.862, 1.0, 1.3):
+        c, a = api.coeffs(u0)
+        co, ao = oracle.coeffs(u0)
+        np.testing.assert_allclose(c, co, rtol=1e-15, atol=0)
+        assert abs(a - ao) <= 1e-15 * max(1, abs(ao))
+    c3 = (ctypes.c_double * 3)()
+    assert L_.sym_coeffs(0.0, c3, None) == -1
+    assert L_.sym_coeffs(float("nan"), c3, None) == -1
+    assert L_.sym_coeffs(-1.0, c3, None) == -1
+    assert L_.sym_coeffs(0.9, None, None) == -2
+
+
+def _dims(*v):
+    return (ctypes.c_int32 * 4)(*v)
+
+
+def test_workspace_bytes(L_):
+    ws32 = L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 1)
+    ws64 = L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 2)
+    assert ws32 > 0 and ws64 > ws32
+    # the plaquette-staple buffer dominates: 8 slots x 18 reals per link
+    big = L_.sym_workspace_bytes(_dims(32, 32, 32, 64), 1)
+    assert big >= 4 * 32 * 32 * 32 * 64 * 8 * 18 * 4
+    for bad in [(3, 4, 4, 4), (4, 4, 4, 2), (4, 5, 4, 4), (0, 4, 4, 4)]:
+        assert L_.sym_workspace_bytes(_dims(*bad), 1) == 0
+    assert L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 3) == 0
+    assert L_.sym_workspace_bytes(None, 1) == 0
+    # V/2 must stay below 2^27 sites per parity
+    assert L_.sym_workspace_bytes(_dims(1024, 1024, 16, 32), 1) == 0
+
+
+FAKE = ctypes.c_void_p(0x100000)       # aligned, never dereferenced
+MISALIGNED = ctypes.c_void_p(0x100008)
+HUGE = 1 << 60
+
+
+def test_force_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    f = L_.sym_force
+    assert f(_dims(4, 4, 3, 4), 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
+    assert f(None, 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 7, FAKE, FAKE, None, FAKE, HUGE, None) == -1
+    assert f(ok, -0.5, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
+    assert f(ok, 0.8677, math.inf, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, None, FAKE, None, FAKE, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, None, None, FAKE, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, MISALIGNED, FAKE, None, FAKE, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, None, None, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, 16, None) == -3
+
+
+def test_action_and_leapfrog_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    a = L_.sym_action
+    assert a(ok, 0.8677, 3.0, 2, FAKE, None, FAKE, HUGE, None) == -2  # S_dev is required
+    assert a(ok, 0.8677, 3.0, 2, FAKE, FAKE, FAKE, 8, None) == -3
+    assert a(_dims(4, 4, 4, 6), 0.0, 3.0, 2, FAKE, FAKE, FAKE, HUGE, None) == -1
+    m = L_.md_leapfrog
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, math.nan, 3, None, FAKE, HUGE, None) == -1
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, 0.01, -1, None, FAKE, HUGE, None) == -1
+    assert m(ok, 0.8677, 3.0, 2, FAKE, None, 0.01, 3, None, FAKE, HUGE, None) == -2
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, 0.01, 3, None, FAKE, 0, None) == -3
+
+
+def test_layout_and_switch_validation(L_):
+    assert L_.sym_pack(_dims(4, 4, 4, 5), 1, FAKE, FAKE, None) == -1
+    assert L_.sym_pack(_dims(4, 4, 4, 4), 1, None, FAKE, None) == -2
+    assert L_.sym_unpack(_dims(4, 4, 4, 4), 0, FAKE, FAKE, None) == -1
+    assert L_.sym_set_force_algorithm(3) == -1
+    assert L_.sym_set_force_algorithm(0) == 0
+    bad = (ctypes.c_double * 3)(1.0, math.nan, 0.0)
+    assert L_.sym_set_coeffs_override(bad) == -1
+    assert L_.sym_set_coeffs_override(None) == 0
+    for s in (0, -1, -2, -3, -4, -5, 99):
+        assert len(L_.sym_strerror(s)) > 0

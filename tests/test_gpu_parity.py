@@ -1,0 +1,242 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 force and action 1e-12 relative, FP32 force and action 1e-5 relative
+(force: max over links of the Frobenius error / max over links of the reference
+norm). The FP32 gate compares against the oracle evaluated on the same FP32-rounded
+links promoted exactly to FP64; the end-to-end error against the unrounded links is
+printed beside it.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gaugegen
+import oracle
+from oracle import brute
+
+from gpu_util import device, force_errors, from_soa, rounded, soa_reference, to_soa
+
+pytestmark = pytest.mark.gpu
+
+U0, BETA = gaugegen.U0, gaugegen.BETA
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def sym():
+    import paper_1808_02281_amd as m
+
+    device()
+    yield m
+    m.set_force_algorithm("auto")
+    m.set_coeffs_override(None)
+
+
+@pytest.fixture(scope="module")
+def c():
+    return oracle.coeffs(U0)[0]
+
+
+# ------------------------------------------------------------------ layout
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_pack_layout_and_roundtrip(sym, prec):
+    L = (4, 6, 4, 8)
+    U = gaugegen.haar_links(L, 5)
+    dev = device()
+    S = to_soa(sym, U, L, prec, dev)
+    ref = soa_reference(rounded(U, prec), L)
+    np.testing.assert_array_equal(S.cpu().numpy().astype(np.float64), ref)
+    back = sym.unpack(S, L)
+    aos = torch.from_numpy(U).to(torch.complex128 if prec == "f64" else torch.complex64).to(dev)
+    assert torch.equal(back, aos)
+
+
+# ------------------------------------------------------------ small lattices
+
+SMALL = [
+    ("haar_4x4x4x4", (4, 4, 4, 4), None),           # config 1; one partial tile
+    ("thermal_6x6x6x8", (6, 6, 6, 8), 0.4),        # 3 full tiles and a ragged tail per block
+    ("thermal_4x8x6x10", (4, 8, 6, 10), 0.5),      # non-cubic
+]
+
+
+def _field(name, L, eps):
+    return gaugegen.haar_links(L, 0) if eps is None else gaugegen.near_thermal_links(L, eps, 17)
+
+
+@pytest.mark.parametrize("alg", ["direct", "factored"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,L,eps", SMALL)
+def test_force_and_action_parity_small(sym, c, alg, prec, name, L, eps):
+    print(f"case {name} {prec} {alg}", flush=True)
+    sym.set_force_algorithm(alg)
+    U = _field(name, L, eps)
+    Ur = rounded(U, prec)
+    G_ref = oracle.force(Ur, L, c, BETA)
+    S_ref, W_ref = oracle.action(Ur, L, c, BETA)
+    dev = device()
+    Us = to_soa(sym, U, L, prec, dev)
+    F, S = sym.force(Us, L, U0, BETA, with_action=True)
+    Sa = sym.action(Us, L, U0, BETA)
+    G = from_soa(sym, F, L)
+    gmax, rms, worst = force_errors(G, G_ref)
+    S = S.cpu().numpy()
+    Sa = Sa.cpu().numpy()
+    print(f"  force gmax {gmax:.2e} rms {rms:.2e} worst-link {worst:.2e}; "
+          f"S(force) {abs(S[0] - S_ref) / abs(S_ref):.2e} S(action) {abs(Sa[0] - S_ref) / abs(S_ref):.2e}")
+    tol = TOL[prec]
+    assert gmax <= tol
+    assert abs(S[0] - S_ref) <= tol * abs(S_ref)
+    assert abs(Sa[0] - S_ref) <= tol * abs(S_ref)
+    np.testing.assert_allclose(Sa[1:], W_ref, rtol=tol)
+    np.testing.assert_allclose(S[1:], W_ref, rtol=tol)
+    if prec == "f32":
+        e2e = force_errors(G, oracle.force(U, L, c, BETA))[0]
+        print(f"  end-to-end FP32 force error vs unrounded links: {e2e:.2e}")
+
+
+@pytest.mark.parametrize("alg", ["direct", "factored"])
+def test_unit_and_abelian_fields(sym, c, alg):
+    sym.set_force_algorithm(alg)
+    dev = device()
+    L = (4, 4, 4, 4)
+    Us = to_soa(sym, gaugegen.unit_links(L), L, "f64", dev)
+    F, S = sym.force(Us, L, U0, BETA, with_action=True)
+    assert torch.count_nonzero(F).item() == 0
+    assert S[0].item() == 0.0
+    assert sym.action(Us, L, U0, BETA)[0].item() == 0.0
+    L = (8, 4, 6, 4)
+    U = gaugegen.abelian_flux_links(L, 3)
+    phi = 2 * np.pi * 3 / L[0]
+    expect = BETA / 3 * np.prod(L) * (2 * (1 - np.cos(phi)) * (1 + 8 * c[2]) + 4 * c[1] * (1 - np.cos(2 * phi)))
+    Us = to_soa(sym, U, L, "f64", dev)
+    F, S = sym.force(Us, L, U0, BETA, with_action=True)
+    assert abs(S[0].item() - expect) <= 1e-12 * expect
+    assert abs(sym.action(Us, L, U0, BETA)[0].item() - expect) <= 1e-12 * expect
+    assert torch.abs(F).max().item() < 1e-13
+
+
+@pytest.mark.parametrize("alg", ["direct", "factored"])
+def test_wilson_override(sym, alg):
+    """c = (1, 0, 0): the action is the textbook Wilson plaquette action."""
+    sym.set_force_algorithm(alg)
+    L = (4, 4, 6, 4)
+    U = gaugegen.haar_links(L, 3)
+    dev = device()
+    try:
+        sym.set_coeffs_override((1.0, 0.0, 0.0))
+        Us = to_soa(sym, U, L, "f64", dev)
+        F, S = sym.force(Us, L, U0, BETA, with_action=True)
+        Sa = sym.action(Us, L, U0, BETA)
+    finally:
+        sym.set_coeffs_override(None)
+    Sw = brute.wilson_action(U, BETA)
+    assert abs(S[0].item() - Sw) <= 1e-12 * abs(Sw)
+    assert abs(Sa[0].item() - Sw) <= 1e-12 * abs(Sw)
+    G_ref = oracle.force(U, L, [1.0, 0.0, 0.0], BETA)
+    assert force_errors(from_soa(sym, F, L), G_ref)[0] <= 1e-12
+
+
+def test_gauge_covariance_on_gpu(sym, c):
+    L = (4, 6, 4, 4)
+    U = gaugegen.near_thermal_links(L, 0.6, 2)
+    g = gaugegen.gauge_transform(L, 8)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(np.roll(g, -1, axis=3 - mu), -1, -2))
+    dev = device()
+    F1, S1 = sym.force(to_soa(sym, U, L, "f64", dev), L, U0, BETA, with_action=True)
+    F2, S2 = sym.force(to_soa(sym, Ug, L, "f64", dev), L, U0, BETA, with_action=True)
+    G1, G2 = from_soa(sym, F1, L), from_soa(sym, F2, L)
+    expect = g[..., None, :, :] @ G1 @ np.conj(np.swapaxes(g, -1, -2))[..., None, :, :]
+    assert np.abs(G2 - expect).max() <= 1e-13 * np.abs(G1).max()
+    assert abs(S1[0].item() - S2[0].item()) <= 1e-13 * abs(S1[0].item())
+
+
+def test_action_is_deterministic(sym):
+    L = (8, 8, 8, 8)
+    Us = to_soa(sym, gaugegen.near_thermal_links(L, 0.3, 4), L, "f64", device())
+    a = [sym.action(Us, L, U0, BETA).cpu().numpy() for _ in range(2)]
+    b = [sym.force(Us, L, U0, BETA, with_action=True)[1].cpu().numpy() for _ in range(2)]
+    assert np.array_equal(a[0], a[1]) and np.array_equal(b[0], b[1])
+
+
+def test_error_codes_surface(sym):
+    from paper_1808_02281_amd import _lib
+
+    L = (4, 4, 4, 4)
+    Us = to_soa(sym, gaugegen.unit_links(L), L, "f64", device())
+    with pytest.raises(ValueError):
+        sym.force(Us, (4, 4, 4, 6), U0, BETA)
+    with pytest.raises(_lib.SymError) as e:
+        sym.force(Us, L, -1.0, BETA)
+    assert e.value.status == -1
+
+
+# ------------------------------------------------------- 16^3 x 32 (config 2)
+
+@pytest.mark.parametrize("alg", ["direct", "factored"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_parity_16x16x16x32(sym, c, alg, prec):
+    print(f"case thermal_16x16x16x32 {prec} {alg}", flush=True)
+    sym.set_force_algorithm(alg)
+    cfg = gaugegen.CONFIGS["thermal_16x16x16x32"]
+    L = cfg["L"]
+    U = gaugegen.near_thermal_links(L, cfg["eps"], cfg["seed"])
+    Ur = rounded(U, prec)
+    G_ref = oracle.force(Ur, L, c, BETA)
+    S_ref, W_ref = oracle.action(Ur, L, c, BETA)
+    Us = to_soa(sym, U, L, prec, device())
+    F, S = sym.force(Us, L, U0, BETA, with_action=True)
+    Sa = sym.action(Us, L, U0, BETA)
+    G = from_soa(sym, F, L)
+    gmax, rms, worst = force_errors(G, G_ref)
+    S, Sa = S.cpu().numpy(), Sa.cpu().numpy()
+    print(f"  force gmax {gmax:.2e} rms {rms:.2e} worst {worst:.2e}; action(force) {abs(S[0]-S_ref)/S_ref:.2e} "
+          f"action {abs(Sa[0]-S_ref)/S_ref:.2e}", flush=True)
+    assert gmax <= TOL[prec]
+    assert abs(S[0] - S_ref) <= TOL[prec] * abs(S_ref)
+    assert abs(Sa[0] - S_ref) <= TOL[prec] * abs(S_ref)
+
+
+# -------------------------------------------- 32^3 x 64 (config 3), sampled
+
+@pytest.fixture(scope="module")
+def big_field():
+    cfg = gaugegen.CONFIGS["thermal_32x32x32x64"]
+    return cfg["L"], gaugegen.near_thermal_links(cfg["L"], cfg["eps"], cfg["seed"])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_parity_32x32x32x64_sampled(sym, c, big_field, prec):
+    """Full-size force in the launch configuration the benchmark times (auto algorithm),
+    checked on 1024 sampled links and on the whole-lattice action; every link checked for
+    tracelessness and antihermiticity."""
+    print(f"case thermal_32x32x32x64 {prec}", flush=True)
+    sym.set_force_algorithm("auto")
+    L, U = big_field
+    Ur = rounded(U, prec)
+    dev = device()
+    Us = to_soa(sym, U, L, prec, dev)
+    F, S = sym.force(Us, L, U0, BETA, with_action=True)
+    G = sym.unpack(F, L)
+    # structure of every link, on the device
+    Gd = G.to(torch.complex128)
+    herm = torch.abs(Gd + Gd.conj().transpose(-1, -2)).max().item()
+    trace = torch.abs(Gd.diagonal(dim1=-2, dim2=-1).sum(-1)).max().item()
+    scale = torch.abs(Gd).max().item()
+    assert herm <= 1e-15 * scale * (1e8 if prec == "f32" else 1)
+    assert trace <= 1e-14 * scale * (1e8 if prec == "f32" else 1)
+    V = int(np.prod(L))
+    rng = np.random.default_rng(2024)
+    sites = rng.integers(0, V, 1024)
+    mus = rng.integers(0, 4, 1024)
+    G_ref = oracle.force_links(Ur, L, c, BETA, sites, mus)
+    Gs = G.reshape(V, 4, 3, 3)[torch.from_numpy(sites).to(dev), torch.from_numpy(mus).to(dev)]
+    gmax, rms, worst = force_errors(Gs.cpu().numpy().astype(np.complex128), G_ref)
+    S_ref, _ = oracle.action(Ur, L, c, BETA)
+    serr = abs(S[0].item() - S_ref) / abs(S_ref)
+    print(f"  sampled force gmax {gmax:.2e} rms {rms:.2e} worst {worst:.2e}; action {serr:.2e}", flush=True)
+    assert gmax <= TOL[prec]
+    assert serr <= TOL[prec]
