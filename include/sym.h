@@ -7,7 +7,7 @@
  *
  * Conventions
  *   L = {Lx, Ly, Lz, Lt}: lattice dimensions, each even and >= 4, periodic in all four
- *     directions; V = Lx*Ly*Lz*Lt sites, 4V links; V/2 <= 2^27.
+ *     directions; V = Lx*Ly*Lz*Lt sites, 4V links; V/2 <= 2^24.
  *   Directions mu = 0..3 are x, y, z, t; U_{n,mu} lives on the link (n, n+mu) and
  *     U_{n,-mu} = U^dagger_{n-mu,mu}.
  *   prec: SYM_F32 (links, forces and momenta stored as float; products in float; every
@@ -119,9 +119,13 @@ int sym_set_coeffs_override(const double c[3]);
 
 /*
  * Process-wide choice of force algorithm: SYM_ALG_DIRECT multiplies out all 48
- * staples of each link (181 SU(3) products per link); SYM_ALG_FACTORED first forms
- * the 6 plaquette staples of every link and builds rectangles and cube loops from
- * them; SYM_ALG_AUTO (default) picks the faster. SYM_EINVAL for other values.
+ * staples of each link (181 SU(3) products per link) and makes no assumption on the
+ * matrices; SYM_ALG_FACTORED first forms the 6 plaquette staples of every link in the
+ * workspace and builds rectangles and cube loops from them (63 products per link); it
+ * stores each staple as two rows and rebuilds the third, which requires the links to
+ * be special unitary to working precision (as the paper's link variables are, and as
+ * md_leapfrog keeps them). SYM_ALG_AUTO (default) is SYM_ALG_FACTORED.
+ * SYM_EINVAL for other values.
  */
 int sym_set_force_algorithm(int algorithm);
 

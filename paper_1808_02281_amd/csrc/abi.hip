@@ -23,7 +23,7 @@ bool g_override_on = false;
 double g_override[3] = {1.0, 0.0, 0.0};
 std::atomic<int> g_algorithm{SYM_ALG_AUTO};
 
-constexpr long long kMaxVh = 1ll << 27;
+constexpr long long kMaxVh = 1ll << 24;  // keeps every (mu, parity) block below 4 GiB
 
 int make_geom(const int32_t* L, Geom* g) {
   if (L == nullptr) return SYM_ENULL;
@@ -36,6 +36,14 @@ int make_geom(const int32_t* L, Geom* g) {
   for (int a = 0; a < 4; ++a) g->L[a] = L[a];
   g->Vh = (int)(V / 2);
   g->Lxh = L[0] / 2;
+  // t-fastest tile order of the per-link kernels (see link_tile in lattice.hpp)
+  const long long per_slice = V / 2 / L[3];
+  g->tslab = 0;
+  g->cps = 0;
+  if (L[3] % 8 == 0 && per_slice % sym::kBlock == 0) {
+    g->tslab = L[3] / 8;
+    g->cps = (int)(per_slice / sym::kBlock);
+  }
   return SYM_OK;
 }
 
@@ -62,7 +70,7 @@ int make_coeffs(double u0, double beta, Coeffs* c) {
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // Workspace regions: [A: per-workgroup action partials, 3 doubles each]
-// [B: per-workgroup kinetic partials] [C: plaquette staples, 8 slots per link].
+// [B: per-workgroup kinetic partials] [C: plaquette staples, 8 slots of two rows per link].
 struct Workspace {
   double* act;
   double* kin;
@@ -76,7 +84,7 @@ size_t region_a(const Geom& g) {
 size_t region_b(const Geom& g) { return align256(sizeof(double) * (size_t)sym::link_tiles(g)); }
 size_t region_c(const Geom& g, int prec) {
   const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
-  return align256((size_t)8 * g.Vh * 8 * 18 * real);  // 8 staple slots of 18 reals per link
+  return align256((size_t)8 * sym::s8_stride(g) * 8 * 12 * real);  // 8 staple slots of 2 rows per link
 }
 
 size_t ws_bytes_for(const Geom& g, int prec) { return region_a(g) + region_b(g) + region_c(g, prec); }

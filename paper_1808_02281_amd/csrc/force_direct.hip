@@ -116,8 +116,8 @@ template <typename T, ForceOut MODE>
 __global__ __launch_bounds__(kBlock) void force_direct_kernel(Geom g, const T* __restrict__ U, T* __restrict__ out,
                                                               double kick, double* __restrict__ partials, Coeffs c,
                                                               int ntiles) {
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int rho = tile & 3, p = (tile >> 2) & 1, chunk = tile >> 3;
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int rho = lt.mu, p = lt.p, chunk = lt.chunk;
   const int cb = chunk * kBlock + threadIdx.x;
   double tr[3] = {0.0, 0.0, 0.0};
   if (cb < g.Vh) {
@@ -150,13 +150,13 @@ __global__ __launch_bounds__(kBlock) void force_direct_kernel(Geom g, const T* _
     if constexpr (MODE == ForceOut::Store) {
       store_link(dst, g.Vh, cb, G);
     } else {
+      su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
-        cx<T> q = dst[(unsigned)(e * g.Vh + cb)];
-        q.re = T(double(q.re) - kick * double(G.e[e].re));
-        q.im = T(double(q.im) - kick * double(G.e[e].im));
-        dst[(unsigned)(e * g.Vh + cb)] = q;
+        q.e[e].re = T(double(q.e[e].re) - kick * double(G.e[e].re));
+        q.e[e].im = T(double(q.e[e].im) - kick * double(G.e[e].im));
       }
+      store_link(dst, g.Vh, cb, q);
     }
   }
   if (partials != nullptr) block_sum_store<3>(tr, partials + 3 * (size_t)blockIdx.x);

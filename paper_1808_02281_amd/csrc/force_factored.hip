@@ -28,12 +28,19 @@
 // in a3, every cube loop from its 6 links, every plaquette from its 4: see the final
 // reduction (kind 2) in action.hip.
 //
-// Staple storage: S8[mu][p][slot][9][V/2] complex, slot = 2*axis(e) + (e < 0); the two
-// slots with axis(e) = mu are never touched.
+// Staple storage: S8[mu][p][slot][6][V/2 + pad] complex, slot = 2*axis(e) + (e < 0);
+// the two slots with axis(e) = mu are never touched. A staple is a product of three
+// SU(3) links, hence itself in SU(3): only its first two rows are stored and the third
+// is rebuilt on load (lattice.hpp), which cuts the staple traffic by a third. This
+// relies on the links being special unitary to working precision.
 #include "kernels.hpp"
 
 namespace sym {
 namespace {
+
+// Scheduling fence between the groups of loads and products below: keeps the
+// scheduler from hoisting every load of the kernel to the top (which costs occupancy).
+#define SYM_FENCE() __builtin_amdgcn_sched_barrier(0)
 
 // Frame: axis[0] = mu (the link's direction), axis[1..3] = the other axes ascending.
 __device__ __forceinline__ void make_frame(const Geom& g, int mu, const int x[4], int axis[4], Nbr& nb) {
@@ -62,6 +69,7 @@ struct FCtx {
   const T* U;
   const T* S8;
   int Vh;
+  int Ss;  // plane stride of S8 (complex elements)
   int p;
   int axis[4];
   Nbr nb;
@@ -79,8 +87,8 @@ struct FCtx {
     constexpr int dp = offset_parity<D0, D1, D2, D3>();
     const int slot = 2 * axis[EAX] + (ES < 0 ? 1 : 0);
     const cx<T>* blk = reinterpret_cast<const cx<T>*>(S8) +
-                       (size_t)((((axis[AX] * 2) + (p ^ dp)) * 8 + slot) * 9) * (size_t)Vh;
-    return load_link(blk, Vh, nbr_cb<D0, D1, D2, D3>(nb));
+                       (size_t)((((axis[AX] * 2) + (p ^ dp)) * 8 + slot) * 6) * (size_t)Ss;
+    return load_su3_rows(blk, Ss, nbr_cb<D0, D1, D2, D3>(nb));
   }
 };
 
@@ -114,9 +122,9 @@ __device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
     launder(lc);
     const su3<T> s = plaquette_staple<T, J>(lc);
     const int slot = 2 * c.axis[e_axis(J)] + (e_sign(J) < 0 ? 1 : 0);
-    cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((c.axis[0] * 2 + c.p) * 8 + slot) * 9) * (size_t)c.Vh;
-    store_link(dst, c.Vh, cb, s);
-    __builtin_amdgcn_sched_barrier(0);
+    cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((c.axis[0] * 2 + c.p) * 8 + slot) * 6) * (size_t)c.Ss;
+    store_su3_rows(dst, c.Ss, cb, s);
+    SYM_FENCE();
     write_staples<T, J + 1>(c, S8, cb);
   }
 }
@@ -124,8 +132,8 @@ __device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void staples_kernel(Geom g, const T* __restrict__ U, T* __restrict__ S8,
                                                          int ntiles) {
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int mu = tile & 3, p = (tile >> 2) & 1, chunk = tile >> 3;
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int mu = lt.mu, p = lt.p, chunk = lt.chunk;
   const int cb = chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   int x[4];
@@ -134,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void staples_kernel(Geom g, const T* __rest
   c.U = U;
   c.S8 = S8;
   c.Vh = g.Vh;
+  c.Ss = s8_stride(g);
   c.p = p;
   make_frame(g, mu, x, c.axis, c.nb);
   write_staples<T, 0>(c, S8, cb);
@@ -152,7 +161,7 @@ __device__ __forceinline__ void long_side(const FCtx<T>& c, su3<T>& tP, su3<T>& 
     add(tP, sx);
     mac<false, false>(RA, lc.template stap<1, 0, 0, 0, 0, a, s>(), sx);
     mac<false, false>(RB, sx, lc.template stap<-1, 0, 0, 0, 0, a, s>());
-    __builtin_amdgcn_sched_barrier(0);
+    SYM_FENCE();
     long_side<T, J + 1>(c, tP, RA, RB);
   }
 }
@@ -202,7 +211,7 @@ __device__ __forceinline__ void short_side_and_cubes(const FCtx<T>& c, su3<T>& t
     } else {
       mac<true, false>(t, lc.template link<1, e1, e2, e3, a>(), R);
     }
-    __builtin_amdgcn_sched_barrier(0);
+    SYM_FENCE();
     short_side_and_cubes<T, J + 1>(c, t, cR, cC);
   }
 }
@@ -212,8 +221,8 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
                                                                 const T* __restrict__ S8, T* __restrict__ out,
                                                                 double kick, double* __restrict__ partials, Coeffs cf,
                                                                 int ntiles) {
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int mu = tile & 3, p = (tile >> 2) & 1, chunk = tile >> 3;
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int mu = lt.mu, p = lt.p, chunk = lt.chunk;
   const int cb = chunk * kBlock + threadIdx.x;
   double a[3] = {0.0, 0.0, 0.0};
   if (cb < g.Vh) {
@@ -223,6 +232,7 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
     c.U = U;
     c.S8 = S8;
     c.Vh = g.Vh;
+  c.Ss = s8_stride(g);
     c.p = p;
     make_frame(g, mu, x, c.axis, c.nb);
     const T cP = T(cf.c[0]), cR = T(cf.c[1]), cC = T(cf.c[2]);
@@ -249,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
       }
       part = re_tr_mul(u, t);
     }
-    __builtin_amdgcn_sched_barrier(0);
+    SYM_FENCE();
     short_side_and_cubes<T, 0>(c, t, cR, cC);
 
     FCtx<T> lc = c;
@@ -262,13 +272,13 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
     if constexpr (MODE == ForceOut::Store) {
       store_link(dst, g.Vh, cb, G);
     } else {
+      su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
-        cx<T> q = dst[(unsigned)(e * g.Vh + cb)];
-        q.re = T(double(q.re) - kick * double(G.e[e].re));
-        q.im = T(double(q.im) - kick * double(G.e[e].im));
-        dst[(unsigned)(e * g.Vh + cb)] = q;
+        q.e[e].re = T(double(q.e[e].re) - kick * double(G.e[e].re));
+        q.e[e].im = T(double(q.e[e].im) - kick * double(G.e[e].im));
       }
+      store_link(dst, g.Vh, cb, q);
     }
   }
   if (partials != nullptr) block_sum_store<3>(a, partials + 3 * (size_t)blockIdx.x);

@@ -32,7 +32,12 @@ hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, d
 
 // Factored force: plaquette staples first (one pass), then rectangles and cube loops
 // assembled from them (second pass).
-// Staple buffer: 8 slots of 9 complex per link (two slots unused), see force_factored.hip.
+// Staple buffer: 8 slots of 6 complex (two rows) per link (two slots unused), see
+// force_factored.hip.
+// Its element planes are kS8Pad complex numbers longer than V/2 so that the 576 planes
+// do not all start at the same power-of-two alignment.
+constexpr int kS8Pad = 0;
+__host__ __device__ inline int s8_stride(const Geom& g) { return g.Vh + kS8Pad; }
 inline int factored_tiles(const Geom& g) { return link_tiles(g); }
 template <typename T>
 hipError_t launch_staples(const Geom& g, const T* U, T* S8, hipStream_t s);

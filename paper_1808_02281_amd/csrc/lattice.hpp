@@ -22,6 +22,8 @@ struct Geom {
   int L[4];   // Lx, Ly, Lz, Lt
   int Vh;     // V / 2 sites per parity
   int Lxh;    // Lx / 2
+  int tslab;  // t-slices per XCD in the t-fastest tile order (0: plain order)
+  int cps;    // 256-site chunks per t-slice and parity (with tslab > 0)
 };
 
 // Coordinates of checkerboard index cb in parity p.
@@ -80,24 +82,110 @@ __device__ __forceinline__ cx<T>* block_ptr(T* field, int mu, int p, int Vh) {
   return reinterpret_cast<cx<T>*>(field) + (size_t)((mu * 2 + p) * 9) * (size_t)Vh;
 }
 
-// Loads take a wave-uniform base per matrix element (scalar registers) plus one
-// per-lane 32-bit byte offset shared by the nine elements.
+// Link loads and stores are raw buffer operations: one resource descriptor per
+// (mu, p) block (scalar registers), a per-lane 32-bit byte offset shared by the nine
+// matrix elements, and a wave-uniform scalar offset per element. Accesses outside the
+// block return zero (loads) or are dropped (stores) instead of faulting. Blocks stay
+// below 4 GiB because V/2 <= 2^24.
+constexpr int kBufferWord3 = 0x00020000;  // descriptor dword 3 for raw access on gfx9-family GPUs
+
 template <typename T>
-__device__ __forceinline__ su3<T> load_link(const cx<T>* __restrict__ blk, int Vh, int cb) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const cx<T>* blk, int Vh) {
+  const unsigned bytes = 9u * (unsigned)Vh * (unsigned)sizeof(cx<T>);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(blk), (short)0, (int)bytes, kBufferWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ su3<T> load_link(const cx<T>* blk, int Vh, int cb) {
+  const __amdgpu_buffer_rsrc_t r = block_rsrc(blk, Vh);
+  const int voff = cb * (int)sizeof(cx<T>);
   su3<T> u;
-  const unsigned off = (unsigned)cb * (unsigned)sizeof(cx<T>);
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
-    const char* base = reinterpret_cast<const char*>(blk + (size_t)c * (size_t)Vh);
-    u.e[c] = *reinterpret_cast<const cx<T>*>(base + off);
+    const int soff = (int)((unsigned)c * (unsigned)Vh * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+      u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   }
   return u;
 }
 
 template <typename T>
-__device__ __forceinline__ void store_link(cx<T>* __restrict__ blk, int Vh, int cb, const su3<T>& u) {
+__device__ __forceinline__ void store_link(cx<T>* blk, int Vh, int cb, const su3<T>& u) {
+  const __amdgpu_buffer_rsrc_t r = block_rsrc(static_cast<const cx<T>*>(blk), Vh);
+  const int voff = cb * (int)sizeof(cx<T>);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) blk[(unsigned)(c * Vh + cb)] = u.e[c];
+  for (int c = 0; c < 9; ++c) {
+    const int soff = (int)((unsigned)c * (unsigned)Vh * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, u.e[c]),
+                                            r, voff, soff, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, u.e[c]),
+                                             r, voff, soff, 0);
+  }
+}
+
+// Special-unitary matrices stored as their first two rows (6 complex numbers): for
+// U in SU(3) the third row is the complex conjugate of the cross product of the first
+// two. Used for intermediate staples, which are products of SU(3) links.
+template <typename T>
+__device__ __forceinline__ cx<T> cross_conj(const cx<T>& a, const cx<T>& b, const cx<T>& c, const cx<T>& d) {
+  // conj(a b - c d)
+  T re = a.re * b.re;
+  re = fma(-a.im, b.im, re);
+  re = fma(-c.re, d.re, re);
+  re = fma(c.im, d.im, re);
+  T im = a.re * b.im;
+  im = fma(a.im, b.re, im);
+  im = fma(-c.re, d.im, im);
+  im = fma(-c.im, d.re, im);
+  return cx<T>{re, -im};
+}
+
+template <typename T>
+__device__ __forceinline__ void complete_third_row(su3<T>& u) {
+  u.e[6] = cross_conj(u.e[1], u.e[5], u.e[2], u.e[4]);
+  u.e[7] = cross_conj(u.e[2], u.e[3], u.e[0], u.e[5]);
+  u.e[8] = cross_conj(u.e[0], u.e[4], u.e[1], u.e[3]);
+}
+
+// Two-row blocks: 6 element planes of `stride` complex numbers each.
+template <typename T>
+__device__ __forceinline__ su3<T> load_su3_rows(const cx<T>* blk, int stride, int cb) {
+  const unsigned bytes = 6u * (unsigned)stride * (unsigned)sizeof(cx<T>);
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(blk), (short)0, (int)bytes, kBufferWord3);
+  const int voff = cb * (int)sizeof(cx<T>);
+  su3<T> u;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int soff = (int)((unsigned)c * (unsigned)stride * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+      u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+  complete_third_row(u);
+  return u;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_su3_rows(cx<T>* blk, int stride, int cb, const su3<T>& u) {
+  const unsigned bytes = 6u * (unsigned)stride * (unsigned)sizeof(cx<T>);
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(blk, (short)0, (int)bytes, kBufferWord3);
+  const int voff = cb * (int)sizeof(cx<T>);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int soff = (int)((unsigned)c * (unsigned)stride * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, u.e[c]),
+                                            r, voff, soff, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, u.e[c]),
+                                             r, voff, soff, 0);
+  }
 }
 
 // XCD-aware tile order. The dispatcher hands consecutive workgroups to the 8 XCDs in
@@ -107,6 +195,30 @@ __device__ __forceinline__ void store_link(cx<T>* __restrict__ blk, int Vh, int 
 __device__ __forceinline__ int xcd_tile(int linear, int ntiles) {
   const int per = ntiles >> 3;
   return (linear & 7) * per + (linear >> 3);
+}
+
+// Per-link kernels: workgroup -> (direction, parity, 256-site chunk). The 8
+// (direction, parity) tiles of a chunk are adjacent. When the lattice allows it
+// (Lt divisible by 8, whole chunks per t-slice) XCD k owns the t-slab
+// [k Lt/8, (k+1) Lt/8) and walks it t-fastest, so that the t-neighbours of the sites
+// in flight were read moments earlier and are still in that XCD's L2.
+struct LinkTile {
+  int mu, p, chunk;
+};
+
+__device__ __forceinline__ LinkTile link_tile(const Geom& g, int linear, int ntiles) {
+  const int tile = xcd_tile(linear, ntiles);
+  LinkTile r;
+  r.mu = tile & 3;
+  r.p = (tile >> 2) & 1;
+  int chunk = tile >> 3;
+  if (g.tslab > 0) {
+    const int per = ntiles >> 6;  // chunks per XCD = tslab * cps
+    const int xcd = chunk / per, j = chunk - xcd * per;
+    chunk = (xcd * g.tslab + j % g.tslab) * g.cps + j / g.tslab;
+  }
+  r.chunk = chunk;
+  return r;
 }
 
 // ------------------------------------------------------------ FP64 reductions

@@ -91,8 +91,8 @@ __device__ __forceinline__ su3<double> to_double(const su3<T>& a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void drift_kernel(Geom g, T* __restrict__ U, const T* __restrict__ P, double dt,
                                                        int ntiles) {
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int mu = tile & 3, p = (tile >> 2) & 1, chunk = tile >> 3;
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int mu = lt.mu, p = lt.p, chunk = lt.chunk;
   const int cb = chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   su3<double> X = to_double(load_link(block_ptr(P, mu, p, g.Vh), g.Vh, cb));
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Geom g, T* __restrict__ U
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kinetic_kernel(Geom g, const T* __restrict__ P, double* __restrict__ partials,
                                                          int ntiles) {
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int mu = tile & 3, p = (tile >> 2) & 1, chunk = tile >> 3;
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int mu = lt.mu, p = lt.p, chunk = lt.chunk;
   const int cb = chunk * kBlock + threadIdx.x;
   double v[1] = {0.0};
   if (cb < g.Vh) {

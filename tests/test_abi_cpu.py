@@ -63,15 +63,17 @@ def test_workspace_bytes(L_):
     ws32 = L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 1)
     ws64 = L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 2)
     assert ws32 > 0 and ws64 > ws32
-    # the plaquette-staple buffer dominates: 8 slots x 18 reals per link
+    # the plaquette-staple buffer dominates: 8 slots x two rows (12 reals) per link
     big = L_.sym_workspace_bytes(_dims(32, 32, 32, 64), 1)
-    assert big >= 4 * 32 * 32 * 32 * 64 * 8 * 18 * 4
+    assert big >= 4 * 32 * 32 * 32 * 64 * 8 * 12 * 4
     for bad in [(3, 4, 4, 4), (4, 4, 4, 2), (4, 5, 4, 4), (0, 4, 4, 4)]:
         assert L_.sym_workspace_bytes(_dims(*bad), 1) == 0
     assert L_.sym_workspace_bytes(_dims(4, 4, 4, 4), 3) == 0
     assert L_.sym_workspace_bytes(None, 1) == 0
-    # V/2 must stay below 2^27 sites per parity
-    assert L_.sym_workspace_bytes(_dims(1024, 1024, 16, 32), 1) == 0
+    # V/2 is limited to 2^24 sites per parity: 64^3 x 128 is the largest 4D lattice of
+    # that volume, one step beyond it is rejected
+    assert L_.sym_workspace_bytes(_dims(64, 64, 64, 128), 1) > 0
+    assert L_.sym_workspace_bytes(_dims(64, 64, 64, 130), 1) == 0
 
 
 FAKE = ctypes.c_void_p(0x100000)       # aligned, never dereferenced
