@@ -96,6 +96,17 @@ int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* 
               size_t ws_bytes, sym_stream_t stream);
 
 /*
+ * Gradient of S_G with respect to the link field, for automatic differentiation:
+ * grad = 2 G U per link (G as in sym_force), the representative of dS/dU on the tangent
+ * space of SU(3) at U. It satisfies dS = Re tr(grad^dagger dU) for every dU = i X U
+ * with X Hermitian and traceless, hence dS/domega^a = -2i tr(T_a G) through any
+ * parametrisation of the links that stays in SU(3) (e.g. U = exp(i omega.T) U0).
+ * Same layout as U; S_dev as in sym_force.
+ */
+int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const void* U, void* grad, double* S_dev,
+                    void* ws, size_t ws_bytes, sym_stream_t stream);
+
+/*
  * nsteps leapfrog steps of the molecular dynamics of H = sum_links -tr(Pi^2) + S_G,
  * with U-dot = Pi U and Pi-dot = -G (U = exp(i omega.T), dU/domega = iTU; Sec. II):
  * per step Pi -= dt/2 G(U); U <- exp(dt Pi) U; Pi -= dt/2 G(U), consecutive half kicks

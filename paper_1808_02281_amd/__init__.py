@@ -6,6 +6,7 @@ The computation is in hand-written HIP kernels behind the C ABI of include/sym.h
 """
 from .api import (  # noqa: F401
     action,
+    action_grad,
     coeffs,
     field_shape,
     force,
@@ -22,3 +23,4 @@ from .api import (  # noqa: F401
     workspace,
     workspace_bytes,
 )
+from .autograd import symanzik_action  # noqa: F401,E402

@@ -131,6 +131,19 @@ def force(U, L, u0, beta, with_action=False, out=None):
     return (F, S) if with_action else F
 
 
+def action_grad(U, L, u0, beta, with_action=False):
+    """2 G U on every link: dS_G/dU projected on the tangent space of SU(3) at U."""
+    _check_field("U", U, L)
+    prec = prec_of(U.dtype)
+    ws = workspace(L, prec, U.device)
+    gr = torch.empty_like(U)
+    S = torch.empty(4, dtype=torch.float64, device=U.device) if with_action else None
+    _lib.check("sym_action_grad", _lib.lib().sym_action_grad(_lib.dims(L), float(u0), float(beta), prec, _ptr(U),
+                                                             _ptr(gr), _ptr(S) if S is not None else None,
+                                                             _ptr(ws), ws.numel(), _stream(U.device)))
+    return (gr, S) if with_action else gr
+
+
 def md_leapfrog(U, P, L, u0, beta, dt, nsteps, with_energy=True):
     """In-place leapfrog on (U, P); returns H = [H_start, H_end] (float64 CUDA tensor)."""
     _check_field("U", U, L)

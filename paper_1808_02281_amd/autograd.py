@@ -1,0 +1,69 @@
+"""Differentiable access to the Symanzik action.
+
+``symanzik_action(U, L, u0, beta)`` returns S_G (a 0-d float64 CUDA tensor) for a link
+field in the SoA even-odd layout; its backward runs the force kernels
+(sym_action_grad), which return 2 G U per link: the gradient of S_G with respect to
+the link matrices, projected on the tangent space of SU(3) at U. Derivatives along
+any parametrisation that keeps the links in SU(3) -- for instance
+U = exp(i omega.T) U0 built with torch ops -- are therefore exact, and
+dS/domega^a = -2i tr(T_a G) at omega = 0 (arXiv:1808.02281 Sec. II, eq. 18_7_25_1 with
+dU/domega = iTU). Components normal to the group (moving U off SU(3)) are not
+represented.
+
+``pack``/``unpack`` are the layout kernels as differentiable permutations, so a
+canonical complex field built in torch can be fed to the action and differentiated.
+"""
+import torch
+
+from . import api
+
+
+class _Pack(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, aos, L):
+        ctx.L = tuple(L)
+        return api.pack(aos.contiguous(), ctx.L)
+
+    @staticmethod
+    def backward(ctx, g):
+        # the real SoA gradient holds dL/dRe and dL/dIm; unpacking it gives the complex
+        # gradient dL/dRe + i dL/dIm that torch expects for complex inputs
+        return api.unpack(g.contiguous(), ctx.L), None
+
+
+class _Unpack(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, soa, L):
+        ctx.L = tuple(L)
+        return api.unpack(soa.contiguous(), ctx.L)
+
+    @staticmethod
+    def backward(ctx, g):
+        return api.pack(g.contiguous(), ctx.L), None
+
+
+class SymanzikAction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U, L, u0, beta):
+        ctx.save_for_backward(U)
+        ctx.args = (tuple(L), float(u0), float(beta))
+        return api.action(U, ctx.args[0], u0, beta)[0]
+
+    @staticmethod
+    def backward(ctx, gS):
+        (U,) = ctx.saved_tensors
+        L, u0, beta = ctx.args
+        grad = api.action_grad(U, L, u0, beta)
+        return grad * gS.to(grad.dtype), None, None, None
+
+
+def pack(aos, L):
+    return _Pack.apply(aos, L)
+
+
+def unpack(soa, L):
+    return _Unpack.apply(soa, L)
+
+
+def symanzik_action(U, L, u0, beta):
+    return SymanzikAction.apply(U, L, u0, beta)

@@ -179,6 +179,16 @@ int do_force(const Geom& g, const Coeffs& c, const void* U, void* F, double* S_d
 }
 
 template <typename T>
+int do_action_grad(const Geom& g, const Coeffs& c, const void* U, void* grad, double* S_dev, const Workspace& w,
+                   hipStream_t s) {
+  hipError_t e = force_into<T>(g, static_cast<const T*>(U), static_cast<T*>(grad), 0.0, S_dev ? w.act : nullptr, c,
+                               ForceOut::Grad, w, s);
+  if (e == hipSuccess && S_dev)
+    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, force_tiles(g), force_kind(), g, c, S_dev, s); });
+  return hip_status(e);
+}
+
+template <typename T>
 int do_action(const Geom& g, const Coeffs& c, const void* U, double* S_dev, const Workspace& w, hipStream_t s) {
   hipError_t e = timed("action", s, [&] { return sym::launch_action<T>(g, static_cast<const T*>(U), w.act, s); });
   if (e == hipSuccess)
@@ -262,6 +272,20 @@ int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* 
   const Workspace w = carve(ws, g);
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return prec == SYM_F64 ? do_force<double>(g, c, U, F, S_dev, w, s) : do_force<float>(g, c, U, F, S_dev, w, s);
+}
+
+int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const void* U, void* grad, double* S_dev,
+                    void* ws, size_t ws_bytes, sym_stream_t stream) {
+  Geom g;
+  Coeffs c;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
+      (rc = check_ptr(grad)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)))
+    return rc;
+  const Workspace w = carve(ws, g);
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return prec == SYM_F64 ? do_action_grad<double>(g, c, U, grad, S_dev, w, s)
+                         : do_action_grad<float>(g, c, U, grad, S_dev, w, s);
 }
 
 int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,

@@ -149,6 +149,14 @@ __global__ __launch_bounds__(kBlock) void force_direct_kernel(Geom g, const T* _
     cx<T>* dst = block_ptr(out, rho, p, g.Vh);
     if constexpr (MODE == ForceOut::Store) {
       store_link(dst, g.Vh, cb, G);
+    } else if constexpr (MODE == ForceOut::Grad) {
+      su3<T> gr = mul<false, false>(G, u);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        gr.e[e].re *= T(2);
+        gr.e[e].im *= T(2);
+      }
+      store_link(dst, g.Vh, cb, gr);
     } else {
       su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
 #pragma unroll
@@ -170,8 +178,10 @@ hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, d
   const int nt = link_tiles(g);
   if (mode == ForceOut::Store)
     force_direct_kernel<T, ForceOut::Store><<<nt, kBlock, 0, s>>>(g, U, out, kick, partials, c, nt);
-  else
+  else if (mode == ForceOut::Kick)
     force_direct_kernel<T, ForceOut::Kick><<<nt, kBlock, 0, s>>>(g, U, out, kick, partials, c, nt);
+  else
+    force_direct_kernel<T, ForceOut::Grad><<<nt, kBlock, 0, s>>>(g, U, out, kick, partials, c, nt);
   return hipGetLastError();
 }
 

@@ -271,6 +271,14 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
     cx<T>* dst = block_ptr(out, mu, p, g.Vh);
     if constexpr (MODE == ForceOut::Store) {
       store_link(dst, g.Vh, cb, G);
+    } else if constexpr (MODE == ForceOut::Grad) {
+      su3<T> gr = mul<false, false>(G, u);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        gr.e[e].re *= T(2);
+        gr.e[e].im *= T(2);
+      }
+      store_link(dst, g.Vh, cb, gr);
     } else {
       su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
 #pragma unroll
@@ -299,8 +307,10 @@ hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out,
   const int nt = factored_tiles(g);
   if (mode == ForceOut::Store)
     force_factored_kernel<T, ForceOut::Store><<<nt, kBlock, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
-  else
+  else if (mode == ForceOut::Kick)
     force_factored_kernel<T, ForceOut::Kick><<<nt, kBlock, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
+  else
+    force_factored_kernel<T, ForceOut::Grad><<<nt, kBlock, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
   return hipGetLastError();
 }
 

@@ -16,8 +16,10 @@ struct Coeffs {
   double beta;
 };
 
-// What a force kernel does with G = (beta/6)(U t)_TA.
-enum class ForceOut { Store = 0, Kick = 1 };
+// What a force kernel does with G = (beta/6)(U t)_TA: store it, subtract kick * G from
+// the momenta in `out`, or store the gradient of S_G with respect to U projected on the
+// tangent space of SU(3) at U, 2 G U (see sym_action_grad).
+enum class ForceOut { Store = 0, Kick = 1, Grad = 2 };
 
 // Number of workgroups of a per-link launch (a multiple of 8: 4 directions x 2 parities).
 inline int link_tiles(const Geom& g) { return ((g.Vh + kBlock - 1) / kBlock) * 8; }
