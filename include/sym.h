@@ -117,6 +117,34 @@ int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const 
 int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,
                 double* H_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
 
+/*
+ * Batched force: the forces (and optionally the actions) of n independent lattices of
+ * any valid shapes, sharing u0, beta and prec, with one launch per pass for every 64
+ * lattices: persistent workgroups walk the concatenated link tiles of all lattices with
+ * a static schedule, so the result does not depend on timing and each link's force is
+ * the same as sym_force's with SYM_ALG_FACTORED. The work table is passed by value in
+ * the kernel arguments, so a call may be captured into a HIP graph (with the same
+ * workspace) and replayed. L: host array of n x 4 dims. U, F: host arrays of n device
+ * pointers (fields as in sym_force). S_dev: NULL or 4n device doubles, {S, W_P, W_R, W_C}
+ * per lattice. ws: at least sym_batch_workspace_bytes(n, L, prec) bytes (0 if invalid).
+ * The schedule (number of persistent workgroups, tile order) is the one
+ * sym_batch_autotune chose for these shapes and precision in this process, else a
+ * default of one resident wave of workgroups with an XCD-contiguous order.
+ */
+size_t sym_batch_workspace_bytes(int n, const int32_t* L, int prec);
+int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
+                    double* S_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
+
+/*
+ * Autotuner for sym_force_batch: times every candidate schedule (256..4096 persistent
+ * workgroups x two tile orders) on the caller's fields (F is overwritten), synchronising
+ * the stream, keeps the fastest for later calls with the same shapes and precision
+ * (in-process cache), and returns it through grid_out / order_out (nullable). Not for
+ * use under graph capture.
+ */
+int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
+                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out);
+
 /* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);

@@ -7,6 +7,8 @@ The computation is in hand-written HIP kernels behind the C ABI of include/sym.h
 from .api import (  # noqa: F401
     action,
     action_grad,
+    batch_autotune,
+    force_batch,
     coeffs,
     field_shape,
     force,

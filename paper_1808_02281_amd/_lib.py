@@ -30,6 +30,9 @@ EXPORTS = (
     "sym_strerror",
     "sym_profile_enable",
     "sym_profile_collect",
+    "sym_batch_workspace_bytes",
+    "sym_force_batch",
+    "sym_batch_autotune",
 )
 
 
@@ -81,6 +84,14 @@ def lib():
     L.sym_profile_enable.restype = ctypes.c_int
     L.sym_profile_collect.argtypes = [ctypes.c_int, ctypes.c_char_p, dp, i32p]
     L.sym_profile_collect.restype = ctypes.c_int
+    L.sym_batch_workspace_bytes.argtypes = [ctypes.c_int, i32p, ctypes.c_int]
+    L.sym_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.sym_force_batch.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp,
+                                  ctypes.c_size_t, vp]
+    L.sym_force_batch.restype = ctypes.c_int
+    L.sym_batch_autotune.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp,
+                                     ctypes.c_size_t, vp, i32p, i32p]
+    L.sym_batch_autotune.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -191,3 +191,68 @@ def profile_collect(max_kinds=32):
         name = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
         out[name] = (ms[k], cnt[k])
     return out
+
+
+def _batch_args(Us, Ls):
+    n = len(Us)
+    if n == 0 or len(Ls) != n:
+        raise ValueError("need one lattice shape per field")
+    for i, (U, L) in enumerate(zip(Us, Ls)):
+        _check_field(f"U[{i}]", U, L)
+        if U.dtype != Us[0].dtype or U.device != Us[0].device:
+            raise ValueError("all fields of a batch must share dtype and device")
+    Lflat = (ctypes.c_int32 * (4 * n))(*[int(v) for L in Ls for v in L])
+    return n, Lflat, prec_of(Us[0].dtype)
+
+
+def batch_workspace(Ls, prec, device):
+    device = torch.device(device)
+    key = ("batch", device.index, tuple(tuple(int(v) for v in L) for L in Ls), int(prec))
+    ws = _WS_CACHE.get(key)
+    if ws is None:
+        n = len(Ls)
+        Lflat = (ctypes.c_int32 * (4 * n))(*[int(v) for L in Ls for v in L])
+        nb = int(_lib.lib().sym_batch_workspace_bytes(n, Lflat, int(prec)))
+        if nb == 0:
+            raise ValueError("invalid batch")
+        ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = ws
+    return ws
+
+
+def force_batch(Us, Ls, u0, beta, with_action=False, out=None, S_out=None):
+    """Forces of many independent lattices in one launch per pass (sym_force_batch).
+
+    Returns the list of force fields (``out`` if given) and, with_action, a float64
+    (n, 4) tensor of S, W_P, W_R, W_C per lattice (``S_out`` if given)."""
+    n, Lflat, prec = _batch_args(Us, Ls)
+    dev = Us[0].device
+    ws = batch_workspace(Ls, prec, dev)
+    Fs = [torch.empty_like(U) for U in Us] if out is None else out
+    for i, (F, L) in enumerate(zip(Fs, Ls)):
+        _check_field(f"out[{i}]", F, L)
+    S = None
+    if with_action:
+        S = torch.empty((n, 4), dtype=torch.float64, device=dev) if S_out is None else S_out
+    Up = (ctypes.c_void_p * n)(*[U.data_ptr() for U in Us])
+    Fp = (ctypes.c_void_p * n)(*[F.data_ptr() for F in Fs])
+    _lib.check("sym_force_batch", _lib.lib().sym_force_batch(n, Lflat, float(u0), float(beta), prec, Up, Fp,
+                                                             _ptr(S) if S is not None else None, _ptr(ws),
+                                                             ws.numel(), _stream(dev)))
+    return (Fs, S) if with_action else Fs
+
+
+def batch_autotune(Us, Ls, u0, beta):
+    """Time the candidate schedules of force_batch for this batch; the best one is kept
+    for later force_batch calls with the same lattice shapes. Returns (grid, order)."""
+    n, Lflat, prec = _batch_args(Us, Ls)
+    dev = Us[0].device
+    ws = batch_workspace(Ls, prec, dev)
+    Fs = [torch.empty_like(U) for U in Us]
+    Up = (ctypes.c_void_p * n)(*[U.data_ptr() for U in Us])
+    Fp = (ctypes.c_void_p * n)(*[F.data_ptr() for F in Fs])
+    grid, order = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check("sym_batch_autotune", _lib.lib().sym_batch_autotune(n, Lflat, float(u0), float(beta), prec, Up, Fp,
+                                                                   _ptr(ws), ws.numel(), _stream(dev),
+                                                                   ctypes.byref(grid), ctypes.byref(order)))
+    return grid.value, order.value

@@ -31,6 +31,8 @@ UNITS = [
     ("force_direct.hip", ["-DSYM_ONLY_F64"], "force_direct_f64.o"),
     ("force_factored.hip", ["-DSYM_ONLY_F32"], "force_factored_f32.o"),
     ("force_factored.hip", ["-DSYM_ONLY_F64"], "force_factored_f64.o"),
+    ("force_batch.hip", ["-DSYM_ONLY_F32"], "force_batch_f32.o"),
+    ("force_batch.hip", ["-DSYM_ONLY_F64"], "force_batch_f64.o"),
 ]
 
 

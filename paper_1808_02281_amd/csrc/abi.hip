@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -227,9 +228,179 @@ int do_leapfrog(const Geom& g, const Coeffs& c, void* Uv, void* Pv, double dt, i
   return hip_status(e);
 }
 
+// ------------------------------------------------------------ batched force
+// Workspace: [partials: 3 doubles per tile of the largest launch chunk]
+//            [per lattice: plaquette-staple buffer, 256-byte aligned]
+struct BatchPlan {
+  std::vector<Geom> g;
+  std::vector<size_t> s8_off;
+  size_t part_bytes = 0;
+  size_t total = 0;
+};
+
+int batch_plan(int n, const int32_t* L, int prec, BatchPlan* plan) {
+  if (n < 1) return SYM_EINVAL;
+  if (L == nullptr) return SYM_ENULL;
+  int rc = check_prec(prec);
+  if (rc != SYM_OK) return rc;
+  plan->g.resize(n);
+  plan->s8_off.resize(n);
+  long long max_chunk_tiles = 0;
+  for (int c0 = 0; c0 < n; c0 += sym::kMaxBatch) {
+    long long tiles = 0;
+    for (int i = c0; i < n && i < c0 + sym::kMaxBatch; ++i) {
+      if ((rc = make_geom(L + 4 * i, &plan->g[i])) != SYM_OK) return rc;
+      tiles += sym::link_tiles(plan->g[i]);
+    }
+    if (tiles > (1ll << 30)) return SYM_EINVAL;
+    max_chunk_tiles = tiles > max_chunk_tiles ? tiles : max_chunk_tiles;
+  }
+  plan->part_bytes = align256(sizeof(double) * 3 * (size_t)max_chunk_tiles);
+  size_t off = plan->part_bytes;
+  for (int i = 0; i < n; ++i) {
+    plan->s8_off[i] = off;
+    off += region_c(plan->g[i], prec);
+  }
+  plan->total = off;
+  return SYM_OK;
+}
+
+struct Schedule {
+  int grid;
+  int order;
+};
+std::mutex g_tune_mu;
+std::map<std::vector<int>, Schedule> g_tune;
+
+std::vector<int> tune_key(int n, const int32_t* L, int prec) {
+  std::vector<int> k{prec, n};
+  for (int i = 0; i < 4 * n; ++i) k.push_back(L[i]);
+  return k;
+}
+
+Schedule default_schedule(int prec) {
+  // one wave of workgroups: 3 (FP32) or 2 (FP64) resident 256-thread groups per CU
+  return Schedule{prec == SYM_F64 ? 512 : 768, 1};
+}
+
+template <typename T>
+hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const void* const* U, void* const* F,
+                           double* S_dev, void* ws, const Schedule& sch, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  double* parts = reinterpret_cast<double*>(base);
+  hipError_t e = hipSuccess;
+  for (int c0 = 0; c0 < n && e == hipSuccess; c0 += sym::kMaxBatch) {
+    sym::BatchTable b;
+    memset(&b, 0, sizeof b);
+    b.n = (n - c0) < sym::kMaxBatch ? (n - c0) : sym::kMaxBatch;
+    b.order = sch.order;
+    int tiles = 0;
+    for (int k = 0; k < b.n; ++k) {
+      const int i = c0 + k;
+      sym::BatchEntry& en = b.e[k];
+      en.U = U[i];
+      en.F = F[i];
+      en.S8 = base + plan.s8_off[i];
+      for (int a = 0; a < 4; ++a) en.L[a] = plan.g[i].L[a];
+      en.Vh = plan.g[i].Vh;
+      en.tile_begin = tiles;
+      tiles += sym::link_tiles(plan.g[i]);
+    }
+    b.total_tiles = tiles;
+    e = timed("staples_batch", s, [&] { return sym::launch_staples_batch<T>(b, sch.grid, s); });
+    if (e == hipSuccess) e = timed("force_batch", s, [&] { return sym::launch_force_batch<T>(b, sch.grid, parts, c, s); });
+    if (e == hipSuccess && S_dev)
+      e = timed("finish_batch", s, [&] { return sym::launch_finish_batch(b, parts, c, S_dev + 4 * c0, s); });
+  }
+  return e;
+}
+
+int check_batch_ptrs(int n, const void* const* U, void* const* F) {
+  if (U == nullptr || F == nullptr) return SYM_ENULL;
+  int rc;
+  for (int i = 0; i < n; ++i)
+    if ((rc = check_ptr(U[i])) || (rc = check_ptr(F[i]))) return rc;
+  return SYM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t sym_batch_workspace_bytes(int n, const int32_t* L, int prec) {
+  BatchPlan plan;
+  return batch_plan(n, L, prec, &plan) == SYM_OK ? plan.total : 0;
+}
+
+int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
+                    double* S_dev, void* ws, size_t ws_bytes, sym_stream_t stream) {
+  BatchPlan plan;
+  Coeffs c;
+  int rc;
+  if ((rc = batch_plan(n, L, prec, &plan)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_batch_ptrs(n, U, F)) ||
+      (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ptr(ws)))
+    return rc;
+  if (ws_bytes < plan.total) return SYM_EWORKSPACE;
+  Schedule sch = default_schedule(prec);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(n, L, prec));
+    if (it != g_tune.end()) sch = it->second;
+  }
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e = prec == SYM_F64 ? force_batch_run<double>(n, plan, c, U, F, S_dev, ws, sch, s)
+                                       : force_batch_run<float>(n, plan, c, U, F, S_dev, ws, sch, s);
+  return hip_status(e);
+}
+
+int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
+                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out) {
+  BatchPlan plan;
+  Coeffs c;
+  int rc;
+  if ((rc = batch_plan(n, L, prec, &plan)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_batch_ptrs(n, U, F)) ||
+      (rc = check_ptr(ws)))
+    return rc;
+  if (ws_bytes < plan.total) return SYM_EWORKSPACE;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return SYM_EHIP;
+  Schedule best = default_schedule(prec);
+  float best_ms = -1.0f;
+  const int grids[] = {256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+  hipError_t e = hipSuccess;
+  for (int order = 0; order < 2 && e == hipSuccess; ++order)
+    for (int grid : grids) {
+      const Schedule sch{grid, order};
+      auto run = [&] {
+        return prec == SYM_F64 ? force_batch_run<double>(n, plan, c, U, F, nullptr, ws, sch, s)
+                               : force_batch_run<float>(n, plan, c, U, F, nullptr, ws, sch, s);
+      };
+      if ((e = run()) != hipSuccess) break;  // warm-up
+      if ((e = hipEventRecord(a, s)) != hipSuccess) break;
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e != hipSuccess) break;
+      if (best_ms < 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best = sch;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return SYM_EHIP;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(n, L, prec)] = best;
+  }
+  if (grid_out) *grid_out = best.grid;
+  if (order_out) *order_out = best.order;
+  return SYM_OK;
+}
+
 
 int sym_coeffs(double u0, double c_out[3], double* alpha_s_out) {
   if (c_out == nullptr) return SYM_ENULL;

@@ -1,0 +1,290 @@
+// Factored gauge force: per-link device code shared by the single-lattice kernels
+// (force_factored.hip) and the batched persistent kernels (force_batch.hip).
+//
+// Factored gauge force. Same result as the direct form (every staple of
+// arXiv:1808.02281 Sec. II, eq. 18_7_25_2), with rectangle and cube staples assembled
+// from plaquette staples instead of multiplied out link by link.
+//
+// Notation: for link (x, mu) and a signed direction e perpendicular to mu,
+//   S(x, mu, e) = U_{x+mu, e} U_{x+e, mu}^dagger U_{x, e}^dagger
+// is the plaquette staple (path e, -mu, -e from x+mu back to x), with
+// U_{y,-nu} = U_{y-nu,nu}^dagger. Inserting U^dagger U = 1 along the paths gives,
+// for the 42 five-link staples of link (x, mu):
+//   rectangles, link first on the long side:  U_{x+mu,mu} S(x+mu,mu,e) S(x,mu,e)
+//   rectangles, link second on the long side: S(x,mu,e) S(x-mu,mu,e) U_{x-mu,mu}
+//   rectangles with the link as short side:   U_{x+mu,e} S(x+e,mu,e) U_{x,e}^dagger
+//   cube loops (e, f, -mu, -e, -f):           U_{x+mu,e} S(x+e,mu,f) S'(x,e,f)
+// where f is perpendicular to mu and to e, and S'(x,e,f) is the path f, -e, -f from
+// x+e to x: S(x,nu,f) for e = +nu, S(x-nu,nu,f)^dagger for e = -nu. Sums over e and f
+// are taken before the shared outer factors are applied.
+//
+// Pass 1 (staples_kernel) writes the six S(x,mu,e) of every link to the workspace:
+// 12 SU(3) products per link. Pass 2 (force_factored_kernel) reads them and forms
+//   t = c_P sum_e S + c_R (rect sums) + (c_R short-side rect + c_C cube sums):
+// 6+1 and 6+1 products for the long-side rectangles, 6 x (1 + 4 + 1) for the rest,
+// plus U t: 51 products. 63 products per link in all, against 181 for the direct form.
+//
+// Action: per link the kernel emits three deficit sums
+//   a1 = 18 - Re tr(U t_P), a2 = 36 - Re tr(U t_RA+RB), a3 = 18 c_R + 72 c_C - Re tr(U t_mix)
+// (t_mix = short-side rectangles weighted c_R plus cubes weighted c_C). Every
+// rectangle is seen from its 4 long-side links in a2 and from its 2 short-side links
+// in a3, every cube loop from its 6 links, every plaquette from its 4: see the final
+// reduction (kind 2) in action.hip.
+//
+// Staple storage: S8[mu][p][slot][6][V/2 + pad] complex, slot = 2*axis(e) + (e < 0);
+// the two slots with axis(e) = mu are never touched. A staple is a product of three
+// SU(3) links, hence itself in SU(3): only its first two rows are stored and the third
+// is rebuilt on load (lattice.hpp), which cuts the staple traffic by a third. This
+// relies on the links being special unitary to working precision.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sym {
+namespace factored {
+
+// Scheduling fence between the groups of loads and products below: keeps the
+// scheduler from hoisting every load of the kernel to the top (which costs occupancy).
+#define SYM_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+// Frame: axis[0] = mu (the link's direction), axis[1..3] = the other axes ascending.
+__device__ __forceinline__ void make_frame(const Geom& g, int mu, const int x[4], int axis[4], Nbr& nb) {
+  axis[0] = mu;
+  axis[1] = mu == 0 ? 1 : 0;
+  axis[2] = mu <= 1 ? 2 : 1;
+  axis[3] = mu <= 2 ? 3 : 2;
+  Nbr full;
+  make_nbr(g, x, full);
+#pragma unroll
+  for (int fa = 0; fa < 4; ++fa) {
+    const int a = axis[fa];
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+      nb.o[fa][d] = a == 0 ? full.o[0][d] : a == 1 ? full.o[1][d] : a == 2 ? full.o[2][d] : full.o[3][d];
+  }
+}
+
+// Signed direction e_J, J = 0..5: frame axis 1 + J/2, sign + for even J.
+constexpr int e_axis(int J) { return 1 + J / 2; }
+constexpr int e_sign(int J) { return (J & 1) ? -1 : 1; }
+constexpr int comp(int fa, int which) { return fa == which ? 1 : 0; }
+
+template <typename T>
+struct FCtx {
+  const T* U;
+  const T* S8;
+  int Vh;
+  int Ss;  // plane stride of S8 (complex elements)
+  int p;
+  int axis[4];
+  Nbr nb;
+
+  // U_{x+d, axis[AX]} (forward link)
+  template <int D0, int D1, int D2, int D3, int AX>
+  __device__ __forceinline__ su3<T> link() const {
+    constexpr int dp = offset_parity<D0, D1, D2, D3>();
+    return load_link(block_ptr(U, axis[AX], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
+  }
+
+  // S(x+d, axis[AX], e) for e = sign ES along frame axis EAX
+  template <int D0, int D1, int D2, int D3, int AX, int EAX, int ES>
+  __device__ __forceinline__ su3<T> stap() const {
+    constexpr int dp = offset_parity<D0, D1, D2, D3>();
+    const int slot = 2 * axis[EAX] + (ES < 0 ? 1 : 0);
+    const cx<T>* blk = reinterpret_cast<const cx<T>*>(S8) +
+                       (size_t)((((axis[AX] * 2) + (p ^ dp)) * 8 + slot) * 6) * (size_t)Ss;
+    return load_su3_rows(blk, Ss, nbr_cb<D0, D1, D2, D3>(nb));
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void launder(FCtx<T>& c) {
+  asm volatile("" : "+s"(c.U));
+  asm volatile("" : "+s"(c.S8));
+}
+
+// ---------------------------------------------------------------- pass 1
+
+template <typename T, int J>
+__device__ __forceinline__ su3<T> plaquette_staple(const FCtx<T>& c) {
+  constexpr int a = e_axis(J);
+  constexpr int a1 = comp(1, a), a2 = comp(2, a), a3 = comp(3, a);
+  if constexpr (e_sign(J) > 0) {
+    // U_{x+mu,a} U_{x+a,mu}^dag U_{x,a}^dag
+    const su3<T> m = mul<false, true>(c.template link<1, 0, 0, 0, a>(), c.template link<0, a1, a2, a3, 0>());
+    return mul<false, true>(m, c.template link<0, 0, 0, 0, a>());
+  } else {
+    // U_{x+mu-a,a}^dag U_{x-a,mu}^dag U_{x-a,a}
+    const su3<T> m = mul<true, true>(c.template link<1, -a1, -a2, -a3, a>(), c.template link<0, -a1, -a2, -a3, 0>());
+    return mul<false, false>(m, c.template link<0, -a1, -a2, -a3, a>());
+  }
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
+  if constexpr (J < 6) {
+    FCtx<T> lc = c;
+    launder(lc);
+    const su3<T> s = plaquette_staple<T, J>(lc);
+    const int slot = 2 * c.axis[e_axis(J)] + (e_sign(J) < 0 ? 1 : 0);
+    cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((c.axis[0] * 2 + c.p) * 8 + slot) * 6) * (size_t)c.Ss;
+    store_su3_rows(dst, c.Ss, cb, s);
+    SYM_FENCE();
+    write_staples<T, J + 1>(c, S8, cb);
+  }
+}
+
+
+// ---------------------------------------------------------------- pass 2
+
+// Long-side rectangles: RA += S(x+mu,mu,e) S(x,mu,e), RB += S(x,mu,e) S(x-mu,mu,e), tP += S(x,mu,e).
+template <typename T, int J>
+__device__ __forceinline__ void long_side(const FCtx<T>& c, su3<T>& tP, su3<T>& RA, su3<T>& RB) {
+  if constexpr (J < 6) {
+    FCtx<T> lc = c;
+    launder(lc);
+    constexpr int a = e_axis(J), s = e_sign(J);
+    const su3<T> sx = lc.template stap<0, 0, 0, 0, 0, a, s>();
+    add(tP, sx);
+    mac<false, false>(RA, lc.template stap<1, 0, 0, 0, 0, a, s>(), sx);
+    mac<false, false>(RB, sx, lc.template stap<-1, 0, 0, 0, 0, a, s>());
+    SYM_FENCE();
+    long_side<T, J + 1>(c, tP, RA, RB);
+  }
+}
+
+// Q += sum over f perpendicular to mu and e of S(x+e,mu,f) S'(x,e,f).
+template <typename T, int J, int K>
+__device__ __forceinline__ void cube_sum(const FCtx<T>& c, su3<T>& Q) {
+  if constexpr (K < 6) {
+    constexpr int a = e_axis(J), s = e_sign(J), fa = e_axis(K), fs = e_sign(K);
+    if constexpr (fa != a) {
+      constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
+      const su3<T> left = c.template stap<0, e1, e2, e3, 0, fa, fs>();
+      if constexpr (s > 0) {
+        mac<false, false>(Q, left, c.template stap<0, 0, 0, 0, a, fa, fs>());
+      } else {
+        mac<false, true>(Q, left, c.template stap<0, e1, e2, e3, a, fa, fs>());
+      }
+    }
+    cube_sum<T, J, K + 1>(c, Q);
+  }
+}
+
+// t += U_{x+mu,e} [ c_R S(x+e,mu,e) U_{x,e}^dag + c_C sum_f S(x+e,mu,f) S'(x,e,f) ]
+template <typename T, int J>
+__device__ __forceinline__ void short_side_and_cubes(const FCtx<T>& c, su3<T>& t, T cR, T cC) {
+  if constexpr (J < 6) {
+    FCtx<T> lc = c;
+    launder(lc);
+    constexpr int a = e_axis(J), s = e_sign(J);
+    constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
+    su3<T> Q;
+    set_zero(Q);
+    cube_sum<T, J, 0>(lc, Q);
+    su3<T> R;
+    if constexpr (s > 0) {
+      R = mul<false, true>(lc.template stap<0, e1, e2, e3, 0, a, s>(), lc.template link<0, 0, 0, 0, a>());
+    } else {
+      R = mul<false, false>(lc.template stap<0, e1, e2, e3, 0, a, s>(), lc.template link<0, e1, e2, e3, a>());
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      R.e[i].re = fma(cC, Q.e[i].re, cR * R.e[i].re);
+      R.e[i].im = fma(cC, Q.e[i].im, cR * R.e[i].im);
+    }
+    if constexpr (s > 0) {
+      mac<false, false>(t, lc.template link<1, 0, 0, 0, a>(), R);
+    } else {
+      mac<true, false>(t, lc.template link<1, e1, e2, e3, a>(), R);
+    }
+    SYM_FENCE();
+    short_side_and_cubes<T, J + 1>(c, t, cR, cC);
+  }
+}
+
+// Pass 1 for link (mu, p, cb) of lattice g: its six plaquette staples into S8.
+template <typename T>
+__device__ __forceinline__ void staples_link(const Geom& g, const T* U, T* S8, int mu, int p, int cb) {
+  int x[4];
+  cb_coords(g, p, cb, x);
+  FCtx<T> c;
+  c.U = U;
+  c.S8 = S8;
+  c.Vh = g.Vh;
+  c.Ss = s8_stride(g);
+  c.p = p;
+  make_frame(g, mu, x, c.axis, c.nb);
+  write_staples<T, 0>(c, S8, cb);
+}
+
+// Pass 2 for link (mu, p, cb): force epilogue per MODE, deficit partials into a[3].
+template <typename T, ForceOut MODE>
+__device__ __forceinline__ void factored_link(const Geom& g, const T* U, const T* S8, T* out, double kick,
+                                              const Coeffs& cf, int mu, int p, int cb, double a[3]) {
+  int x[4];
+  cb_coords(g, p, cb, x);
+  FCtx<T> c;
+  c.U = U;
+  c.S8 = S8;
+  c.Vh = g.Vh;
+  c.Ss = s8_stride(g);
+  c.p = p;
+  make_frame(g, mu, x, c.axis, c.nb);
+  const T cP = T(cf.c[0]), cR = T(cf.c[1]), cC = T(cf.c[2]);
+
+  su3<T> t;
+  double part;  // Re tr(U t) before the short-side rectangles and cubes are added
+  {
+    su3<T> tP, RA, RB;
+    set_zero(tP);
+    set_zero(RA);
+    set_zero(RB);
+    long_side<T, 0>(c, tP, RA, RB);
+    FCtx<T> lc = c;
+    launder(lc);
+    const su3<T> u = lc.template link<0, 0, 0, 0, 0>();
+    su3<T> WR = mul<false, false>(lc.template link<1, 0, 0, 0, 0>(), RA);  // U_{x+mu,mu} RA
+    mac<false, false>(WR, RB, lc.template link<-1, 0, 0, 0, 0>());         // + RB U_{x-mu,mu}
+    a[0] = 18.0 - re_tr_mul(u, tP);
+    a[1] = 36.0 - re_tr_mul(u, WR);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      t.e[i].re = fma(cP, tP.e[i].re, cR * WR.e[i].re);
+      t.e[i].im = fma(cP, tP.e[i].im, cR * WR.e[i].im);
+    }
+    part = re_tr_mul(u, t);
+  }
+  SYM_FENCE();
+  short_side_and_cubes<T, 0>(c, t, cR, cC);
+
+  FCtx<T> lc = c;
+  launder(lc);
+  const su3<T> u = lc.template link<0, 0, 0, 0, 0>();
+  const su3<T> B = mul<false, false>(u, t);
+  a[2] = 18.0 * cf.c[1] + 72.0 * cf.c[2] - (re_tr(B) - part);
+  const su3<T> G = ta_scaled(B, T(cf.beta / 6.0));
+  cx<T>* dst = block_ptr(out, mu, p, g.Vh);
+  if constexpr (MODE == ForceOut::Store) {
+    store_link(dst, g.Vh, cb, G);
+  } else if constexpr (MODE == ForceOut::Grad) {
+    su3<T> gr = mul<false, false>(G, u);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      gr.e[e].re *= T(2);
+      gr.e[e].im *= T(2);
+    }
+    store_link(dst, g.Vh, cb, gr);
+  } else {
+    su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      q.e[e].re = T(double(q.e[e].re) - kick * double(G.e[e].re));
+      q.e[e].im = T(double(q.e[e].im) - kick * double(G.e[e].im));
+    }
+    store_link(dst, g.Vh, cb, q);
+  }
+}
+
+}  // namespace factored
+}  // namespace sym

@@ -41,11 +41,47 @@ hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, d
 constexpr int kS8Pad = 0;
 __host__ __device__ inline int s8_stride(const Geom& g) { return g.Vh + kS8Pad; }
 inline int factored_tiles(const Geom& g) { return link_tiles(g); }
+// Dynamic LDS reserved by the factored force launches to cap resident workgroups per
+// CU (160 KiB of LDS per CU): 56 KiB -> 2 workgroups (FP32), 96 KiB -> 1 (FP64).
+template <typename T>
+constexpr size_t factored_lds_reservation() {
+  return sizeof(T) == 4 ? 56 * 1024 : 96 * 1024;
+}
 template <typename T>
 hipError_t launch_staples(const Geom& g, const T* U, T* S8, hipStream_t s);
 template <typename T>
 hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out, double kick,
                                  double* partials, const Coeffs& c, ForceOut mode, hipStream_t s);
+
+// Batched factored force over many independent lattices (force_batch.hip). The work
+// table travels by value in the kernel arguments, so a captured launch holds no host
+// pointers. Tiles of all lattices are concatenated (tile_begin ascending); persistent
+// workgroups walk them with a static schedule:
+//   order 0: tile = blockIdx + k * grid;
+//   order 1: XCD x (= blockIdx % 8) owns the x-th eighth of the tiles, walked in order.
+constexpr int kMaxBatch = 64;
+struct BatchEntry {
+  const void* U;
+  void* F;
+  void* S8;
+  int L[4];
+  int Vh;
+  int tile_begin;
+};
+struct BatchTable {
+  int n;
+  int total_tiles;
+  int order;
+  int pad;
+  BatchEntry e[kMaxBatch];
+};
+template <typename T>
+hipError_t launch_staples_batch(const BatchTable& b, int grid, hipStream_t s);
+template <typename T>
+hipError_t launch_force_batch(const BatchTable& b, int grid, double* partials, const Coeffs& c, hipStream_t s);
+// One block per lattice: per-lattice action from the pass-2 partials (kind 2).
+hipError_t launch_finish_batch(const BatchTable& b, const double* partials, const Coeffs& c, double* out,
+                               hipStream_t s);
 
 // Action: loop products per site; W partials per workgroup.
 int action_tiles(const Geom& g);

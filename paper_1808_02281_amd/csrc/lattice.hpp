@@ -253,6 +253,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
       v[k] = s;
     }
   }
+  __syncthreads();  // red[] may be reused by the next call in the same block
 }
 
 // block_sum, then thread 0 writes the N sums to out[0..N).
