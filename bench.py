@@ -31,8 +31,8 @@ FLOP_STAPLES = 2376         # factored pass 1: 6 plaquette staples x 2 products
 FLOP_FACTORED = 11494       # factored pass 2: 51 products + sums, traces, TA
 FLOP_DIRECT = 36940         # direct kernel: 181 products + sums, traces, TA
 # Minimum HBM bytes per link of each kernel (read once / write once), per real size r.
-BYTES_STAPLES = lambda r: (18 + 6 * 18) * r              # read U, write 6 staples
-BYTES_FACTORED = lambda r: (18 + 6 * 18 + 18) * r        # read U and own staples, write G
+BYTES_STAPLES = lambda r: (18 + 6 * 12) * r              # read U, write 6 two-row staples
+BYTES_FACTORED = lambda r: (18 + 6 * 12 + 18) * r        # read U and own staples, write G
 BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts packed FMA)
@@ -40,7 +40,7 @@ PEAK_F32_NONPACKED = 78.6e12               # 256 CU x 64 lanes x 2 flop x 2.4 GH
 PEAK_HBM = 8.0e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_factored_f32_32x32x32x64_traffic.json")
-KERNEL_SOURCES = ["force_factored.hip", "su3.hpp", "lattice.hpp", "kernels.hpp"]
+KERNEL_SOURCES = ["force_factored.hip", "factored.hpp", "su3.hpp", "lattice.hpp", "kernels.hpp"]
 
 
 def kernel_source_hash():
@@ -92,6 +92,67 @@ def time_force(sym, torch, U, L, u0, beta, steps, warmup):
     return ms, wall, kernels, F, float(S[0].item())
 
 
+def bench_batch(sym, torch, gaugegen, u0, beta, reps=20):
+    """64 independent lattices of uneven sizes (8^4, 12^4, 16^3x32; eps in [0.2, 0.4]),
+    FP32 force with FP64 action: per-lattice calls against one batched launch per pass,
+    eager and replayed from a captured HIP graph."""
+    recipe = gaugegen.batch_recipe(64, 6)
+    dev = torch.device("cuda:0")
+    Ls = [r["L"] for r in recipe]
+    Us = []
+    for i, r in enumerate(recipe):
+        Us.append(sym.pack(gaugegen.near_thermal_links_device(r["L"], r["eps"], r["seed"], dev, torch.complex64),
+                           r["L"]))
+        if i % 16 == 15:
+            torch.cuda.synchronize()
+            log(f"  generated {i + 1} of {len(recipe)} lattices")
+    links = sum(4 * sym.volume(L) for L in Ls)
+    Fs = [torch.empty_like(U) for U in Us]
+    S = torch.empty((len(Us), 4), dtype=torch.float64, device=dev)
+
+    def per_lattice():
+        for U, L, F in zip(Us, Ls, Fs):
+            sym.force(U, L, u0, beta, with_action=True, out=F)
+
+    def batched():
+        sym.force_batch(Us, Ls, u0, beta, with_action=True, out=Fs, S_out=S)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def graphed(fn):
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return timed(g.replay)
+
+    out = {"lattices": len(Us), "links": links, "sizes": {"8^4": Ls.count((8, 8, 8, 8)),
+                                                          "12^4": Ls.count((12, 12, 12, 12)),
+                                                          "16^3x32": Ls.count((16, 16, 16, 32))}}
+    ms = timed(per_lattice)
+    out["per_lattice_eager"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "launches": 3 * len(Us)}
+    ms = graphed(per_lattice)
+    out["per_lattice_graph"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3)}
+    ms = timed(batched)
+    out["batched_default"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "launches": 3}
+    grid, order = sym.batch_autotune(Us, Ls, u0, beta)
+    ms = timed(batched)
+    out["batched_tuned"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "grid": grid, "order": order}
+    ms = graphed(batched)
+    out["batched_tuned_graph"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3)}
+    return out
+
+
 def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
     """The FP64 oracle's force on a random sample of links of the same workload."""
     import numpy as np
@@ -138,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-md", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -158,7 +220,7 @@ def main():
     import paper_1808_02281_amd as sym
 
     if args.only_f32:
-        args.no_cpu_baseline = args.no_fp64 = args.no_md = True
+        args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = True
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]
@@ -264,6 +326,10 @@ def main():
         out["md_leapfrog"] = {"prec": "f32", "nsteps": nst, "dt": 0.02, "ms_per_step": ms / nst,
                               "link_updates_per_s": links * nst / (ms * 1e-3)}
         del P, Um
+
+    if not args.no_batch:
+        log("timing the 64-lattice batch")
+        out["batch"] = bench_batch(sym, torch, gaugegen, u0, beta)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")

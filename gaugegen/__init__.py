@@ -14,6 +14,7 @@ from .fields import (  # noqa: F401
     haar_su3,
     haar_links,
     near_thermal_links,
+    near_thermal_links_device,
     momenta,
     gauge_transform,
     unit_links,

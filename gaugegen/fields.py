@@ -67,6 +67,20 @@ def near_thermal_links(L, eps, seed):
     return _exp_i_hermitian(H)
 
 
+def near_thermal_links_device(L, eps, seed, device, dtype=None):
+    """Recipe G2 with the same seeded normals, exponentiated on `device` with
+    torch.linalg.matrix_exp in complex128 (for large benchmark batches). Equal to
+    near_thermal_links up to rounding; returns a complex128 torch tensor (or dtype)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    r = torch.from_numpy(rng.standard_normal(field_shape(L, (4, 8)))).to(device)
+    T = torch.from_numpy(generators()).to(device)
+    H = eps * torch.einsum("...a,aij->...ij", r.to(T.dtype), T)
+    U = torch.linalg.matrix_exp(1j * H)
+    return U if dtype is None else U.to(dtype)
+
+
 def momenta(L, seed):
     """Config recipe G3: Pi = i sum_a p_a T_a with p_a ~ N(0,1) of shape (..., 4, 8).
 

@@ -279,8 +279,9 @@ std::vector<int> tune_key(int n, const int32_t* L, int prec) {
 }
 
 Schedule default_schedule(int prec) {
-  // one wave of workgroups: 3 (FP32) or 2 (FP64) resident 256-thread groups per CU
-  return Schedule{prec == SYM_F64 ? 512 : 768, 1};
+  // one round of resident workgroups under the occupancy cap of the factored pass:
+  // 2 (FP32) or 1 (FP64) 256-thread groups per CU
+  return Schedule{prec == SYM_F64 ? 256 : 512, 1};
 }
 
 template <typename T>
