@@ -88,6 +88,10 @@ __device__ __forceinline__ cx<T>* block_ptr(T* field, int mu, int p, int Vh) {
 // block return zero (loads) or are dropped (stores) instead of faulting. Blocks stay
 // below 4 GiB because V/2 <= 2^24.
 constexpr int kBufferWord3 = 0x00020000;  // descriptor dword 3 for raw access on gfx9-family GPUs
+// Cache policy of link stores: non-temporal. Every field a kernel writes (staples,
+// forces, updated links) is far larger than L2 and is read by a later kernel, so it
+// should not evict the neighbour links the running kernel is re-reading.
+constexpr int kStoreNT = 2;
 
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const cx<T>* blk, int Vh) {
@@ -120,10 +124,10 @@ __device__ __forceinline__ void store_link(cx<T>* blk, int Vh, int cb, const su3
     const int soff = (int)((unsigned)c * (unsigned)Vh * (unsigned)sizeof(cx<T>));
     if constexpr (sizeof(T) == 4)
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, u.e[c]),
-                                            r, voff, soff, 0);
+                                            r, voff, soff, kStoreNT);
     else
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, u.e[c]),
-                                             r, voff, soff, 0);
+                                             r, voff, soff, kStoreNT);
   }
 }
 
@@ -181,10 +185,10 @@ __device__ __forceinline__ void store_su3_rows(cx<T>* blk, int stride, int cb, c
     const int soff = (int)((unsigned)c * (unsigned)stride * (unsigned)sizeof(cx<T>));
     if constexpr (sizeof(T) == 4)
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, u.e[c]),
-                                            r, voff, soff, 0);
+                                            r, voff, soff, kStoreNT);
     else
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, u.e[c]),
-                                             r, voff, soff, 0);
+                                             r, voff, soff, kStoreNT);
   }
 }
 
