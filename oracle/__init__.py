@@ -1,4 +1,6 @@
-"""FP64 CPU oracle for the one-loop Symanzik gauge action and force (arXiv:1808.02281, Sec. II).
+"""FP64 CPU oracle for the one-loop Symanzik gauge action and force (arXiv:1808.02281, Sec. II)
+and for the asqtad / HISQ fat-link smearing and its path force (Secs. "Asqtad fermion",
+"HISQ fermion").
 
 TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package. It shares no code with the GPU library
@@ -19,6 +21,12 @@ from .oracle import (  # noqa: F401
     kinetic,
     leapfrog,
     num_threads,
+    FAT_CLASSES,
+    fat_paths,
+    fat_links,
+    fat_grad,
+    fat_grad_links,
+    fat_force_from_grad,
     gell_mann,
     lie_derivative,
 )

@@ -92,3 +92,36 @@ def wilson_action(U, beta):
             P = Umu @ Unu_xmu @ np.conj(np.swapaxes(Umu_xnu, -1, -2)) @ np.conj(np.swapaxes(Unu, -1, -2))
             S += (1.0 - np.trace(P, axis1=-2, axis2=-1).real / 3.0).sum()
     return beta * S
+
+
+def fat_links(U, c):
+    """Asqtad fat links and Naik long links by spelling out every term of the asqtad matrix.
+
+    V_{n,mu} = c_1 U_{n,mu} + c_3 (three-staples, eq. 18_6_6_4) + c_5 (five-staples,
+    eq. 18_6_6_5) + c_7 (seven-staples, eq. 18_6_6_6) + c_L (Lepage, eq. 18_6_6_7);
+    W_{n,mu} = c_N U_{n,mu} U_{n+mu,mu} U_{n+2mu,mu} (eq. 18_6_6_3). The transverse
+    directions are enumerated with itertools, each term walked as shifted link fields.
+    """
+    import itertools
+
+    c1, c3, c5, c7, cL, cN = c
+    V = np.zeros_like(U)
+    W = np.zeros_like(U)
+    signs = (1, -1)
+    for mu in range(4):
+        others = [a for a in range(4) if a != mu]
+        acc = c1 * U[..., mu, :, :]
+        for nu in others:
+            for s in signs:
+                acc = acc + c3 * _walk(U, [(nu, s), (mu, 1), (nu, -s)])
+                acc = acc + cL * _walk(U, [(nu, s), (nu, s), (mu, 1), (nu, -s), (nu, -s)])
+        for nu, rho in itertools.permutations(others, 2):
+            for s1, s2 in itertools.product(signs, signs):
+                acc = acc + c5 * _walk(U, [(nu, s1), (rho, s2), (mu, 1), (rho, -s2), (nu, -s1)])
+        for nu, rho, sg in itertools.permutations(others, 3):
+            for s1, s2, s3 in itertools.product(signs, signs, signs):
+                acc = acc + c7 * _walk(U, [(nu, s1), (rho, s2), (sg, s3), (mu, 1), (sg, -s3), (rho, -s2),
+                                           (nu, -s1)])
+        V[..., mu, :, :] = acc
+        W[..., mu, :, :] = cN * _walk(U, [(mu, 1), (mu, 1), (mu, 1)])
+    return V, W

@@ -51,6 +51,17 @@ def _load():
     lib.orc_leapfrog.argtypes = [_c_int32_p, _c_double_p, ctypes.c_double, vp, vp, ctypes.c_double,
                                  ctypes.c_int32, _c_double_p]
     lib.orc_leapfrog.restype = ctypes.c_int
+    lib.orc_fat_paths.argtypes = [ctypes.c_int32, _c_int32_p, _c_int32_p, _c_int32_p]
+    lib.orc_fat_paths.restype = ctypes.c_int
+    lib.orc_fat_links.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp]
+    lib.orc_fat_links.restype = None
+    lib.orc_fat_grad.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp, vp]
+    lib.orc_fat_grad.restype = None
+    lib.orc_fat_grad_links.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp, ctypes.c_int64, _c_int64_p,
+                                       _c_int32_p, vp]
+    lib.orc_fat_grad_links.restype = None
+    lib.orc_fat_force_from_grad.argtypes = [ctypes.c_int64, vp, vp, vp]
+    lib.orc_fat_force_from_grad.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -159,6 +170,74 @@ def leapfrog(U, P, L, c, beta, dt, nsteps):
     if rc != 0:
         raise MemoryError("oracle leapfrog could not allocate its force buffer")
     return U, P, H[0], H[1]
+
+
+FAT_CLASSES = ("one-link", "three-staple", "five-staple", "seven-staple", "Lepage", "Naik")
+
+
+def _c6(c):
+    if len(c) != 6:
+        raise ValueError("fat-link coefficients are (c_1, c_3, c_5, c_7, c_L, c_N)")
+    return (ctypes.c_double * 6)(*[float(v) for v in c])
+
+
+def fat_paths(mu):
+    """Paths of the asqtad matrix for direction mu (0..3): (len[86], cls[86], dirs[86,7]).
+
+    85 smearing paths from p to p+mu (eq. 18_6_6_7_2 and the Lepage term eq. 18_6_6_7),
+    then the Naik path (eq. 18_6_6_3); classes index FAT_CLASSES; signed directions +-1..+-4.
+    """
+    ln = (ctypes.c_int32 * 86)()
+    cl = (ctypes.c_int32 * 86)()
+    d = (ctypes.c_int32 * (86 * 7))()
+    n = _load().orc_fat_paths(int(mu), ln, cl, d)
+    return np.array(ln[:n]), np.array(cl[:n]), np.array(d[:]).reshape(86, 7)[:n]
+
+
+def fat_links(U, L, c):
+    """(V, W): fat links and Naik long links (c_N included) of every link, shapes like U."""
+    U = _field(U, L)
+    V = np.empty_like(U)
+    W = np.empty_like(U)
+    _load().orc_fat_links(_dims(L), _c6(c), U.ctypes.data, V.ctypes.data, W.ctypes.data)
+    return V, W
+
+
+def fat_grad(U, L, c, GV, GW=None):
+    """grad of Phi = Re sum tr(GV^+ V) + Re sum tr(GW^+ W) w.r.t. U (dRe + i dIm), every link."""
+    U = _field(U, L)
+    GV = _field(GV, L)
+    GWp = None if GW is None else _field(GW, L)
+    out = np.empty_like(U)
+    _load().orc_fat_grad(_dims(L), _c6(c), U.ctypes.data, GV.ctypes.data,
+                         None if GWp is None else GWp.ctypes.data, out.ctypes.data)
+    return out
+
+
+def fat_grad_links(U, L, c, GV, GW, sites, mus):
+    """fat_grad on a list of links (lexicographic site, direction): shape (n, 3, 3)."""
+    U = _field(U, L)
+    GV = _field(GV, L)
+    GWp = None if GW is None else _field(GW, L)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    out = np.empty((len(sites), 3, 3), dtype=np.complex128)
+    _load().orc_fat_grad_links(_dims(L), _c6(c), U.ctypes.data, GV.ctypes.data,
+                               None if GWp is None else GWp.ctypes.data, len(sites),
+                               sites.ctypes.data_as(_c_int64_p), mus.ctypes.data_as(_c_int32_p),
+                               out.ctypes.data)
+    return out
+
+
+def fat_force_from_grad(U, grad):
+    """G = -(1/2)(U grad^+)_TA per link (the gauge-force convention, eq. 18_7_24_6)."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    grad = np.ascontiguousarray(grad, dtype=np.complex128)
+    if U.shape != grad.shape:
+        raise ValueError("U and grad must have the same shape")
+    G = np.empty_like(U)
+    _load().orc_fat_force_from_grad(U.size // 9, U.ctypes.data, grad.ctypes.data, G.ctypes.data)
+    return G
 
 
 def num_threads():
