@@ -145,6 +145,43 @@ int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, c
 int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
                        void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out);
 
+/*
+ * Fat-link smearing of the asqtad and HISQ actions and the force it induces on the thin
+ * links (Sec. "Asqtad fermion": fat link V of eq. 18_6_6_7_2 with the Lepage term of
+ * eq. 18_6_6_7, Naik term of eq. 18_6_6_3; Sec. "HISQ fermion": the pull-back F~ of
+ * eq. 18_7_24_7 and B = U F~^T of eq. 18_7_24_6).
+ *
+ * c: host array {c_1, c_3, c_5, c_7, c_L, c_N}, finite (tadpole factors included by
+ * the caller; the paper gives no values). Per link (x, mu):
+ *   V_{x,mu} = c_1 U_{x,mu} + c_3 (6 three-staples) + c_5 (24 five-staples)
+ *            + c_7 (48 seven-staples) + c_L (6 Lepage paths),  every path x -> x+mu;
+ *   W_{x,mu} = c_N U_{x,mu} U_{x+mu,mu} U_{x+2mu,mu}.
+ * The staggered phases of the fermion matrix are not applied (they belong to the
+ * caller's adjoint fields below). All fields have the link layout of sym_force.
+ *
+ * sym_fat_links: U (read) -> V, W (W may be NULL).
+ *
+ * sym_fat_force: for given adjoint fields GV, GW (device, link layout; GW may be NULL:
+ * no Naik term) differentiates Phi(U) = Re sum tr(GV^dagger V) + Re sum tr(GW^dagger W).
+ * GV is the complex conjugate of the paper's F (eq. 18_7_24_4): F^T = GV^dagger.
+ *   mode SYM_FAT_GRAD:  out = grad with dPhi = Re sum tr(grad^dagger dU) for every
+ *                       complex variation dU (grad = dPhi/dRe U + i dPhi/dIm U, the
+ *                       complex conjugate of the paper's F~): the input of the next
+ *                       level of a smearing chain, and what autograd expects;
+ *   mode SYM_FAT_FORCE: out = G = -(1/2) (U grad^dagger)_TA, traceless antihermitian,
+ *                       with dPhi/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U:
+ *                       the same convention as the gauge force G of sym_force, so the
+ *                       two add.
+ * ws: at least sym_fat_workspace_bytes(L, prec) bytes (18 matrices per link of
+ * intermediate fields). Errors and asynchrony as for sym_force.
+ */
+typedef enum { SYM_FAT_GRAD = 0, SYM_FAT_FORCE = 1 } sym_fat_mode;
+size_t sym_fat_workspace_bytes(const int32_t L[4], int prec);
+int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U, void* V, void* W, void* ws,
+                  size_t ws_bytes, sym_stream_t stream);
+int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U, const void* GV, const void* GW,
+                  void* out, int mode, void* ws, size_t ws_bytes, sym_stream_t stream);
+
 /* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);

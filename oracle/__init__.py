@@ -24,6 +24,7 @@ from .oracle import (  # noqa: F401
     FAT_CLASSES,
     fat_paths,
     fat_links,
+    fat_links_links,
     fat_grad,
     fat_grad_links,
     fat_force_from_grad,

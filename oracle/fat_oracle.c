@@ -301,3 +301,25 @@ void orc_fat_force_from_grad(int64_t nlinks, const cplx *U, const cplx *grad, cp
         st3(G + k * 9, t);
     }
 }
+
+/* V and W of a list of links (site, mu) only; out shapes (n, 3, 3). W may be NULL. */
+void orc_fat_links_links(const int32_t L[4], const double c[6], const cplx *U, int64_t n, const int64_t *sites,
+                         const int32_t *mus, cplx *V, cplx *W) {
+    lat g = mklat(L);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        int mu = mus[i] + 1;
+        fpath P[FAT_NPATH];
+        int np = fat_paths(mu, P);
+        mat3 v = z3();
+        for (int k = 0; k < np; ++k) v = axpy3(v, c[P[k].cls], walk(&g, U, sites[i], P[k].d, 0, P[k].len, NULL));
+        st3(V + i * 9, v);
+        if (W) {
+            const int nk[3] = {mu, mu, mu};
+            mat3 w = walk(&g, U, sites[i], nk, 0, 3, NULL);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) w.a[a][b] *= c[FAT_NAIK];
+            st3(W + i * 9, w);
+        }
+    }
+}

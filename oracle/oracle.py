@@ -55,6 +55,8 @@ def _load():
     lib.orc_fat_paths.restype = ctypes.c_int
     lib.orc_fat_links.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp]
     lib.orc_fat_links.restype = None
+    lib.orc_fat_links_links.argtypes = [_c_int32_p, _c_double_p, vp, ctypes.c_int64, _c_int64_p, _c_int32_p, vp, vp]
+    lib.orc_fat_links_links.restype = None
     lib.orc_fat_grad.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp, vp]
     lib.orc_fat_grad.restype = None
     lib.orc_fat_grad_links.argtypes = [_c_int32_p, _c_double_p, vp, vp, vp, ctypes.c_int64, _c_int64_p,
@@ -200,6 +202,18 @@ def fat_links(U, L, c):
     V = np.empty_like(U)
     W = np.empty_like(U)
     _load().orc_fat_links(_dims(L), _c6(c), U.ctypes.data, V.ctypes.data, W.ctypes.data)
+    return V, W
+
+
+def fat_links_links(U, L, c, sites, mus):
+    """(V, W) on a list of links (lexicographic site, direction): shapes (n, 3, 3)."""
+    U = _field(U, L)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    V = np.empty((len(sites), 3, 3), dtype=np.complex128)
+    W = np.empty_like(V)
+    _load().orc_fat_links_links(_dims(L), _c6(c), U.ctypes.data, len(sites), sites.ctypes.data_as(_c_int64_p),
+                                mus.ctypes.data_as(_c_int32_p), V.ctypes.data, W.ctypes.data)
     return V, W
 
 

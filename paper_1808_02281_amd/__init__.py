@@ -1,5 +1,6 @@
 """MI355X (gfx950) implementation of the one-loop Symanzik improved gauge action, its
-molecular-dynamics force and a leapfrog update (arXiv:1808.02281, Sec. II).
+molecular-dynamics force and a leapfrog update (arXiv:1808.02281, Sec. II), and of the
+asqtad/HISQ fat-link smearing with its path force (Secs. "Asqtad fermion", "HISQ fermion").
 
 The computation is in hand-written HIP kernels behind the C ABI of include/sym.h
 (libsym.so); this package is a thin binding over torch device memory and streams.
@@ -10,6 +11,9 @@ from .api import (  # noqa: F401
     batch_autotune,
     force_batch,
     coeffs,
+    fat_force,
+    fat_links,
+    fat_workspace,
     field_shape,
     force,
     md_leapfrog,
@@ -25,4 +29,4 @@ from .api import (  # noqa: F401
     workspace,
     workspace_bytes,
 )
-from .autograd import symanzik_action  # noqa: F401,E402
+from .autograd import fat_smear, symanzik_action  # noqa: F401,E402

@@ -33,7 +33,11 @@ EXPORTS = (
     "sym_batch_workspace_bytes",
     "sym_force_batch",
     "sym_batch_autotune",
+    "sym_fat_workspace_bytes",
+    "sym_fat_links",
+    "sym_fat_force",
 )
+FAT_MODES = {"grad": 0, "force": 1}
 
 
 class SymError(RuntimeError):
@@ -92,6 +96,12 @@ def lib():
     L.sym_batch_autotune.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp,
                                      ctypes.c_size_t, vp, i32p, i32p]
     L.sym_batch_autotune.restype = ctypes.c_int
+    L.sym_fat_workspace_bytes.argtypes = [i32p, ctypes.c_int]
+    L.sym_fat_workspace_bytes.restype = ctypes.c_size_t
+    L.sym_fat_links.argtypes = [i32p, ctypes.c_int, dp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sym_fat_links.restype = ctypes.c_int
+    L.sym_fat_force.argtypes = [i32p, ctypes.c_int, dp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    L.sym_fat_force.restype = ctypes.c_int
     _lib = L
     return L
 

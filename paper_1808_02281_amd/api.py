@@ -256,3 +256,70 @@ def batch_autotune(Us, Ls, u0, beta):
                                                                    _ptr(ws), ws.numel(), _stream(dev),
                                                                    ctypes.byref(grid), ctypes.byref(order)))
     return grid.value, order.value
+
+
+# ------------------------------------------------------------------ fat links
+
+def _fat_c(c):
+    c = [float(v) for v in c]
+    if len(c) != 6:
+        raise ValueError("fat-link coefficients are (c_1, c_3, c_5, c_7, c_L, c_N)")
+    return (ctypes.c_double * 6)(*c)
+
+
+def fat_workspace(L, prec, device):
+    """A cached device workspace of sym_fat_workspace_bytes(L, prec) bytes."""
+    device = torch.device(device)
+    key = ("fat", device.index, tuple(int(v) for v in L), int(prec))
+    ws = _WS_CACHE.get(key)
+    if ws is None:
+        n = int(_lib.lib().sym_fat_workspace_bytes(_lib.dims(L), int(prec)))
+        if n == 0:
+            raise ValueError(f"invalid lattice {tuple(L)} or precision {prec}")
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = ws
+    return ws
+
+
+def fat_links(U, L, c, with_naik=True, out=None):
+    """Asqtad/HISQ fat links V (and Naik links W) of a link field (sym_fat_links).
+
+    c = (c_1, c_3, c_5, c_7, c_L, c_N). Returns V, or (V, W) with_naik; ``out`` may
+    give V or (V, W)."""
+    _check_field("U", U, L)
+    prec = prec_of(U.dtype)
+    ws = fat_workspace(L, prec, U.device)
+    if out is None:
+        V = torch.empty_like(U)
+        W = torch.empty_like(U) if with_naik else None
+    else:
+        V, W = (out if with_naik else (out, None))
+    _check_field("V", V, L)
+    if W is not None:
+        _check_field("W", W, L)
+    _lib.check("sym_fat_links", _lib.lib().sym_fat_links(_lib.dims(L), prec, _fat_c(c), _ptr(U), _ptr(V),
+                                                         _ptr(W) if W is not None else None, _ptr(ws), ws.numel(),
+                                                         _stream(U.device)))
+    return (V, W) if with_naik else V
+
+
+def fat_force(U, L, c, GV, GW=None, mode="grad", out=None):
+    """Pull-back of the adjoint fields GV (of V) and GW (of W, optional) to the thin links
+    (sym_fat_force): mode 'grad' gives dPhi/dRe U + i dPhi/dIm U, 'force' the traceless
+    antihermitian G = -(1/2)(U grad^+)_TA (gauge-force convention)."""
+    _check_field("U", U, L)
+    _check_field("GV", GV, L)
+    if GW is not None:
+        _check_field("GW", GW, L)
+    for t in (GV, GW):
+        if t is not None and t.dtype != U.dtype:
+            raise TypeError("adjoint fields must have the dtype of U")
+    prec = prec_of(U.dtype)
+    ws = fat_workspace(L, prec, U.device)
+    o = torch.empty_like(U) if out is None else out
+    _check_field("out", o, L)
+    _lib.check("sym_fat_force", _lib.lib().sym_fat_force(_lib.dims(L), prec, _fat_c(c), _ptr(U), _ptr(GV),
+                                                         _ptr(GW) if GW is not None else None, _ptr(o),
+                                                         _lib.FAT_MODES[mode], _ptr(ws), ws.numel(),
+                                                         _stream(U.device)))
+    return o

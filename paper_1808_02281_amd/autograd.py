@@ -67,3 +67,29 @@ def unpack(soa, L):
 
 def symanzik_action(U, L, u0, beta):
     return SymanzikAction.apply(U, L, u0, beta)
+
+
+class FatSmear(torch.autograd.Function):
+    """(V, W) = fat and Naik links of U; backward = the path-force kernels (sym_fat_force)."""
+
+    @staticmethod
+    def forward(ctx, U, L, c):
+        ctx.save_for_backward(U)
+        ctx.args = (tuple(L), tuple(float(v) for v in c))
+        return api.fat_links(U, ctx.args[0], ctx.args[1], with_naik=True)
+
+    @staticmethod
+    def backward(ctx, gV, gW):
+        (U,) = ctx.saved_tensors
+        L, c = ctx.args
+        if gV is None:
+            gV = torch.zeros_like(U)
+        grad = api.fat_force(U, L, c, gV.contiguous(), None if gW is None else gW.contiguous(), mode="grad")
+        return grad, None, None
+
+
+def fat_smear(U, L, c):
+    """Differentiable asqtad/HISQ smearing: (V, W) with V the fat links and W the Naik
+    links of the SoA link field U (real gradient layout as for the fields: the gradient
+    of a real function with respect to the re and im parts of every element)."""
+    return FatSmear.apply(U, L, c)

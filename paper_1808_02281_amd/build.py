@@ -33,6 +33,8 @@ UNITS = [
     ("force_factored.hip", ["-DSYM_ONLY_F64"], "force_factored_f64.o"),
     ("force_batch.hip", ["-DSYM_ONLY_F32"], "force_batch_f32.o"),
     ("force_batch.hip", ["-DSYM_ONLY_F64"], "force_batch_f64.o"),
+    ("fat.hip", ["-DSYM_ONLY_F32"], "fat_f32.o"),
+    ("fat.hip", ["-DSYM_ONLY_F64"], "fat_f64.o"),
 ]
 
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/sym.h"
+#include "fat.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -326,6 +327,68 @@ int check_batch_ptrs(int n, const void* const* U, void* const* F) {
 
 }  // namespace
 
+// ------------------------------------------------------------ fat links
+
+namespace {
+
+size_t link_field_bytes(const Geom& g, int prec) {
+  const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
+  return (size_t)8 * 9 * 2 * real * (size_t)g.Vh;  // 4 directions x 2 parities x 9 complex
+}
+
+size_t fat_ws_bytes(const Geom& g, int prec) { return 18 * align256(link_field_bytes(g, prec)); }
+
+template <typename T>
+sym::fat::Fields<T> fat_carve(void* ws, const Geom& g, int prec) {
+  const size_t one = align256(link_field_bytes(g, prec));
+  char* p = static_cast<char*>(ws);
+  sym::fat::Fields<T> w;
+  w.T1 = reinterpret_cast<T*>(p);
+  w.midc = reinterpret_cast<T*>(p + 6 * one);
+  w.gM = reinterpret_cast<T*>(p + 9 * one);
+  w.ginner = reinterpret_cast<T*>(p + 15 * one);
+  return w;
+}
+
+int fat_coeffs(const double* c, sym::fat::FatCoeffs* out) {
+  if (c == nullptr) return SYM_ENULL;
+  for (int k = 0; k < 6; ++k) {
+    if (!isfinite(c[k])) return SYM_EINVAL;
+    out->c[k] = c[k];
+  }
+  return SYM_OK;
+}
+
+template <typename T>
+int do_fat_links(const Geom& g, const sym::fat::FatCoeffs& c, const void* U, void* V, void* W,
+                 const sym::fat::Fields<T>& w, hipStream_t s) {
+  const T* u = static_cast<const T*>(U);
+  hipError_t e = timed("fat_fk1", s, [&] { return sym::launch_fat_stage<T>(0, g, u, nullptr, nullptr, nullptr, 0, c, w, s); });
+  if (e == hipSuccess)
+    e = timed("fat_fk2", s, [&] { return sym::launch_fat_stage<T>(1, g, u, nullptr, nullptr, nullptr, 0, c, w, s); });
+  if (e == hipSuccess)
+    e = timed("fat_fk3", s, [&] {
+      return sym::launch_fat_fk3<T>(g, u, static_cast<T*>(V), static_cast<T*>(W), c, w, s);
+    });
+  return hip_status(e);
+}
+
+template <typename T>
+int do_fat_force(const Geom& g, const sym::fat::FatCoeffs& c, const void* U, const void* GV, const void* GW,
+                 void* out, int mode, const sym::fat::Fields<T>& w, hipStream_t s) {
+  const T* u = static_cast<const T*>(U);
+  const T* gv = static_cast<const T*>(GV);
+  const T* gw = static_cast<const T*>(GW);
+  T* o = static_cast<T*>(out);
+  static const char* names[5] = {"fat_fk1", "fat_fk2", "fat_bk3", "fat_bk2", "fat_gk"};
+  hipError_t e = hipSuccess;
+  for (int stage = 0; stage < 5 && e == hipSuccess; ++stage)
+    e = timed(names[stage], s, [&] { return sym::launch_fat_stage<T>(stage, g, u, gv, gw, o, mode, c, w, s); });
+  return hip_status(e);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t sym_batch_workspace_bytes(int n, const int32_t* L, int prec) {
@@ -501,6 +564,41 @@ int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym
                : sym::launch_unpack<float>(g, static_cast<const float*>(soa), static_cast<float*>(aos_lex), s);
   });
   return hip_status(e);
+}
+
+size_t sym_fat_workspace_bytes(const int32_t L[4], int prec) {
+  Geom g;
+  if (make_geom(L, &g) != SYM_OK || check_prec(prec) != SYM_OK) return 0;
+  return fat_ws_bytes(g, prec);
+}
+
+int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U, void* V, void* W, void* ws,
+                  size_t ws_bytes, sym_stream_t stream) {
+  Geom g;
+  sym::fat::FatCoeffs cf;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = fat_coeffs(c, &cf)) || (rc = check_ptr(U)) ||
+      (rc = check_ptr(V)) || (W && (rc = check_ptr(W))) || (rc = check_ptr(ws)))
+    return rc;
+  if (ws_bytes < fat_ws_bytes(g, prec)) return SYM_EWORKSPACE;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return prec == SYM_F64 ? do_fat_links<double>(g, cf, U, V, W, fat_carve<double>(ws, g, prec), s)
+                         : do_fat_links<float>(g, cf, U, V, W, fat_carve<float>(ws, g, prec), s);
+}
+
+int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U, const void* GV, const void* GW,
+                  void* out, int mode, void* ws, size_t ws_bytes, sym_stream_t stream) {
+  Geom g;
+  sym::fat::FatCoeffs cf;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = fat_coeffs(c, &cf)) || (rc = check_ptr(U)) ||
+      (rc = check_ptr(GV)) || (GW && (rc = check_ptr(GW))) || (rc = check_ptr(out)) || (rc = check_ptr(ws)))
+    return rc;
+  if (mode != SYM_FAT_GRAD && mode != SYM_FAT_FORCE) return SYM_EINVAL;
+  if (ws_bytes < fat_ws_bytes(g, prec)) return SYM_EWORKSPACE;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return prec == SYM_F64 ? do_fat_force<double>(g, cf, U, GV, GW, out, mode, fat_carve<double>(ws, g, prec), s)
+                         : do_fat_force<float>(g, cf, U, GV, GW, out, mode, fat_carve<float>(ws, g, prec), s);
 }
 
 int sym_set_coeffs_override(const double c[3]) {

@@ -1,0 +1,194 @@
+// Fat-link smearing (asqtad / HISQ) and its path force: kernels and launchers.
+// The per-link device code and the derivation are in fat.hpp.
+#include "fat.hpp"
+
+namespace sym {
+
+using fat::Ctx;
+using fat::FatCoeffs;
+using fat::Fields;
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fat_fk1_kernel(Geom g, const T* __restrict__ U, T* __restrict__ T1,
+                                                          int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  fat::fk1_step<1>(c, T1, cb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ T1,
+                                                          T* __restrict__ midc, FatCoeffs cf, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  fat::fk2_step<1>(c, T1, midc, cf, cb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fat_fk3_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ T1,
+                                                          const T* __restrict__ midc, T* __restrict__ V,
+                                                          T* __restrict__ W, FatCoeffs cf, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  const su3<T> u = c.template u<0, 0, 0, 0, 0>();
+  su3<T> acc = u;
+  const T c1 = T(cf.c[0]);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    acc.e[e].re *= c1;
+    acc.e[e].im *= c1;
+  }
+  fat::fk3_step<1>(acc, c, T1, midc, T(cf.c[4]));
+  store_link(block_ptr(V, lt.mu, lt.p, g.Vh), g.Vh, cb, acc);
+  if (W != nullptr) {
+    fat::launder(c);
+    su3<T> w = mul<false, false>(c.template u<0, 0, 0, 0, 0>(), c.template u<1, 0, 0, 0, 0>());
+    w = mul<false, false>(w, c.template u<2, 0, 0, 0, 0>());
+    const T cN = T(cf.c[5]);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      w.e[e].re *= cN;
+      w.e[e].im *= cN;
+    }
+    store_link(block_ptr(W, lt.mu, lt.p, g.Vh), g.Vh, cb, w);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fat_bk3_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ GV,
+                                                          T* __restrict__ gM, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  fat::bk3_step<1>(c, GV, gM, cb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ gM,
+                                                          T* __restrict__ ginner, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  fat::bk2_step<1>(c, gM, ginner, cb);
+}
+
+// Gradient (or force) of the thin link (y, nu): direct terms, transports of U_nu's own
+// chain, Naik terms, and the deposits of the transports along nu of the other chains.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ GV,
+                                                         const T* __restrict__ GW, Fields<T> w, T* __restrict__ out,
+                                                         FatCoeffs cf, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  Ctx<T> c;
+  fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
+  const T c1 = T(cf.c[0]), c3 = T(cf.c[1]), c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]), cN = T(cf.c[5]);
+
+  // direct terms: c1 GV + c3 sum gmid + c5 sum g_inner (all at y, direction nu)
+  su3<T> acc = c.template f<0, 0, 0, 0, 0>(GV, 1, 0);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    acc.e[e].re *= c1;
+    acc.e[e].im *= c1;
+  }
+  for (int j = 0; j < 6; ++j) axpy(acc, c3, c.template f<0, 0, 0, 0, 0>(w.gM, 6, j));
+  for (int j = 0; j < 3; ++j) axpy(acc, c5, c.template f<0, 0, 0, 0, 0>(w.ginner, 3, j));
+  SYM_FAT_FENCE();
+  fat::gk_pull<1>(acc, c, w, c7, cL);
+
+  if (GW != nullptr) {
+    // W_{y-k nu} = cN U_{y-k nu,nu} U_{y-(k-1)nu,nu} U_{y-(k-2)nu,nu} for k = 0, 1, 2
+    Ctx<T> cc = c;
+    fat::launder(cc);
+    const su3<T> u1 = cc.template u<1, 0, 0, 0, 0>(), u2 = cc.template u<2, 0, 0, 0, 0>();
+    su3<T> t = mul<false, true>(cc.template f<0, 0, 0, 0, 0>(GW, 1, 0), u2);
+    su3<T> nk = mul<false, true>(t, u1);
+    const su3<T> um1 = cc.template u<-1, 0, 0, 0, 0>();
+    t = mul<true, false>(um1, cc.template f<-1, 0, 0, 0, 0>(GW, 1, 0));
+    mac<false, true>(nk, t, u1);
+    t = mul<true, true>(um1, cc.template u<-2, 0, 0, 0, 0>());
+    mac<false, false>(nk, t, cc.template f<-2, 0, 0, 0, 0>(GW, 1, 0));
+    axpy(acc, cN, nk);
+    SYM_FAT_FENCE();
+  }
+
+  fat::gk_factor<1>(acc, c, GV, w, cf);
+
+  fat::launder(c);
+  cx<T>* dst = block_ptr(out, lt.mu, lt.p, g.Vh);
+  if constexpr (MODE == 0) {
+    store_link(dst, g.Vh, cb, acc);
+  } else {
+    // G = -(1/2)(U grad^dagger)_TA, the force in the convention of the gauge force
+    const su3<T> b = mul<false, true>(c.template u<0, 0, 0, 0, 0>(), acc);
+    store_link(dst, g.Vh, cb, ta_scaled(b, T(-0.5)));
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fat_fk3(const Geom& g, const T* U, T* V, T* W, const FatCoeffs& c, const Fields<T>& w,
+                          hipStream_t s) {
+  const int nt = link_tiles(g);
+  fat_fk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, w.midc, V, W, c, nt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fat_stage(int stage, const Geom& g, const T* U, const T* GV, const T* GW, T* out, int mode,
+                            const FatCoeffs& c, const Fields<T>& w, hipStream_t s) {
+  const int nt = link_tiles(g);
+  switch (stage) {
+    case 0:
+      fat_fk1_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, nt);
+      break;
+    case 1:
+      fat_fk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, w.midc, c, nt);
+      break;
+    case 2:
+      fat_bk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, GV, w.gM, nt);
+      break;
+    case 3:
+      fat_bk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.gM, w.ginner, nt);
+      break;
+    default:
+      if (mode == 0)
+        fat_gk_kernel<T, 0><<<nt, kBlock, 0, s>>>(g, U, GV, GW, w, out, c, nt);
+      else
+        fat_gk_kernel<T, 1><<<nt, kBlock, 0, s>>>(g, U, GV, GW, w, out, c, nt);
+      break;
+  }
+  return hipGetLastError();
+}
+
+#ifndef SYM_ONLY_F64
+template hipError_t launch_fat_fk3<float>(const Geom&, const float*, float*, float*, const FatCoeffs&,
+                                            const Fields<float>&, hipStream_t);
+template hipError_t launch_fat_stage<float>(int, const Geom&, const float*, const float*, const float*, float*, int,
+                                            const FatCoeffs&, const Fields<float>&, hipStream_t);
+#endif
+#ifndef SYM_ONLY_F32
+template hipError_t launch_fat_fk3<double>(const Geom&, const double*, double*, double*, const FatCoeffs&,
+                                             const Fields<double>&, hipStream_t);
+template hipError_t launch_fat_stage<double>(int, const Geom&, const double*, const double*, const double*, double*,
+                                             int, const FatCoeffs&, const Fields<double>&, hipStream_t);
+#endif
+
+}  // namespace sym

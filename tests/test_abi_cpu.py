@@ -121,3 +121,26 @@ def test_layout_and_switch_validation(L_):
     assert L_.sym_set_coeffs_override(None) == 0
     for s in (0, -1, -2, -3, -4, -5, 99):
         assert len(L_.sym_strerror(s)) > 0
+
+
+def test_fat_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    c = (ctypes.c_double * 6)(5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
+    # 18 link fields of intermediates
+    n32 = L_.sym_fat_workspace_bytes(ok, 1)
+    assert n32 >= 18 * 4 * 256 * 9 * 8
+    assert L_.sym_fat_workspace_bytes(ok, 2) >= 2 * 18 * 4 * 256 * 9 * 8
+    assert L_.sym_fat_workspace_bytes(_dims(4, 4, 4, 3), 1) == 0
+    fl = L_.sym_fat_links
+    assert fl(ok, 1, None, FAKE, FAKE, None, FAKE, HUGE, None) == -2
+    bad = (ctypes.c_double * 6)(1, 0, 0, math.inf, 0, 0)
+    assert fl(ok, 1, bad, FAKE, FAKE, None, FAKE, HUGE, None) == -1
+    assert fl(ok, 1, c, FAKE, None, None, FAKE, HUGE, None) == -2
+    assert fl(ok, 1, c, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
+    assert fl(ok, 1, c, FAKE, FAKE, None, FAKE, 64, None) == -3
+    ff = L_.sym_fat_force
+    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, 2, FAKE, HUGE, None) == -1   # mode
+    assert ff(ok, 1, c, FAKE, None, None, FAKE, 0, FAKE, HUGE, None) == -2   # GV required
+    assert ff(ok, 1, c, FAKE, FAKE, None, None, 0, FAKE, HUGE, None) == -2   # out required
+    assert ff(ok, 3, c, FAKE, FAKE, None, FAKE, 0, FAKE, HUGE, None) == -1
+    assert ff(ok, 2, c, FAKE, FAKE, FAKE, FAKE, 1, FAKE, 8, None) == -3

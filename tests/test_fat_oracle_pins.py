@@ -228,3 +228,16 @@ def test_gradient_linear_in_adjoint_and_class_additive():
         c[k] = C_GENERIC[k]
         parts = parts + oracle.fat_grad(U, L, c, G1)
     np.testing.assert_allclose(parts, oracle.fat_grad(U, L, C_GENERIC, G1), atol=1e-12)
+
+
+def test_sampled_links_equal_full():
+    L = (4, 6, 4, 4)
+    rng = np.random.default_rng(16)
+    U = gaugegen.haar_links(L, 10)
+    V, W = oracle.fat_links(U, L, C_GENERIC)
+    n = L[0] * L[1] * L[2] * L[3]
+    sites = rng.integers(0, n, 30)
+    mus = rng.integers(0, 4, 30)
+    Vs, Ws = oracle.fat_links_links(U, L, C_GENERIC, sites, mus)
+    np.testing.assert_array_equal(Vs, V.reshape(n, 4, 3, 3)[sites, mus])
+    np.testing.assert_array_equal(Ws, W.reshape(n, 4, 3, 3)[sites, mus])
