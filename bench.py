@@ -35,6 +35,15 @@ BYTES_STAPLES = lambda r: (18 + 6 * 12) * r              # read U, write 6 two-r
 BYTES_FACTORED = lambda r: (18 + 6 * 12 + 18) * r        # read U and own staples, write G
 BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 
+# Fat-link path force (asqtad/HISQ smearing), flop per link of each kernel, counted from
+# the kernel source: SU(3) product 198, product accumulated into a matrix 216, matrix
+# axpy 36, matrix scaling 18 (see the design notes for the per-kernel breakdown).
+FAT_FLOP = {"fat_fk1": 2592, "fat_fk2": 6102, "fat_fk3": 3348, "fat_bk3": 2700, "fat_bk2": 5832,
+            "fat_gk": 30456}
+# minimum HBM matrices (18 reals) read + written per link by each kernel
+FAT_MATRICES = {"fat_fk1": 7, "fat_fk2": 10, "fat_fk3": 12, "fat_bk3": 8, "fat_bk2": 10, "fat_gk": 22}
+C_ASQTAD = (5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
+
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts packed FMA)
 PEAK_F32_NONPACKED = 78.6e12               # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_HBM = 8.0e12
@@ -153,6 +162,90 @@ def bench_batch(sym, torch, gaugegen, u0, beta, reps=20):
     return out
 
 
+def bench_fat(sym, torch, U_np, L, steps, warmup, with_fp64=True, with_cpu=True, budget_s=8.0):
+    """Fat-link path force on the same lattice: synthetic adjoint fields GV, GW (complex
+    Gaussian per matrix element, seed 7, standing in for the fermion outer products),
+    asqtad coefficients; one step = sym_fat_force in gradient mode (5 kernels)."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    V = int(np.prod(L))
+    links = 4 * V
+    rng = np.random.default_rng(7)
+    shape = U_np.shape
+    GV_np = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+    GW_np = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+    out = {"workload": f"{WORKLOAD}, adjoint fields complex Gaussian (seed 7), asqtad coefficients",
+           "coefficients": list(C_ASQTAD)}
+    for prec, cdt in (("f32", torch.complex64), ("f64", torch.complex128)):
+        if prec == "f64" and not with_fp64:
+            continue
+        U = sym.pack(torch.from_numpy(U_np).to(dev).to(cdt), L)
+        GV = sym.pack(torch.from_numpy(GV_np).to(dev).to(cdt), L)
+        GW = sym.pack(torch.from_numpy(GW_np).to(dev).to(cdt), L)
+        g = torch.empty_like(U)
+        for _ in range(warmup):
+            sym.fat_force(U, L, C_ASQTAD, GV, GW, mode="grad", out=g)
+        torch.cuda.synchronize()
+        sym.profile_enable(True)
+        sym.profile_collect()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            sym.fat_force(U, L, C_ASQTAD, GV, GW, mode="grad", out=g)
+        e1.record()
+        torch.cuda.synchronize()
+        kern = sym.profile_collect()
+        ms = e0.elapsed_time(e1) / steps
+        # forward smearing (fat and Naik links)
+        Vf, Wf = torch.empty_like(U), torch.empty_like(U)
+        sym.fat_links(U, L, C_ASQTAD, out=(Vf, Wf))
+        torch.cuda.synchronize()
+        sym.profile_collect()
+        e0.record()
+        for _ in range(steps):
+            sym.fat_links(U, L, C_ASQTAD, out=(Vf, Wf))
+        e1.record()
+        torch.cuda.synchronize()
+        kern_f = sym.profile_collect()
+        sym.profile_enable(False)
+        ms_f = e0.elapsed_time(e1) / steps
+        r = 4 if prec == "f32" else 8
+        per = {}
+        for name, (tot, n) in list(kern.items()) + [(k, v) for k, v in kern_f.items() if k == "fat_fk3"]:
+            t = tot / n * 1e-3
+            per[name] = {"ms": t * 1e3, "tflops": FAT_FLOP[name] * links / t / 1e12,
+                         "min_hbm_tbs": FAT_MATRICES[name] * 18 * r * links / t / 1e12}
+        gk = per["fat_gk"]
+        peak = PEAK[prec]
+        res = {"value": links / (ms * 1e-3), "unit": "link-forces/s", "ms_per_step": ms,
+               "fat_links_ms": ms_f, "kernels": per,
+               "roofline": {"kernel": "fat_gk", "bound": "alu", "achieved": gk["tflops"], "peak": peak / 1e12,
+                            "unit": "TFLOP/s", "frac": gk["tflops"] * 1e12 / peak,
+                            "flop_per_link": FAT_FLOP["fat_gk"],
+                            "hbm_min_bytes_per_link": FAT_MATRICES["fat_gk"] * 18 * r,
+                            "hbm_frac_at_min_bytes": gk["min_hbm_tbs"] * 1e12 / PEAK_HBM}}
+        out[prec] = res
+        log(f"  fat path force {prec}: {ms:.3f} ms/step, fat links {ms_f:.3f} ms; {per}")
+        del U, GV, GW, g, Vf, Wf
+    if with_cpu:
+        import oracle
+
+        n = 64
+        while True:
+            sites = rng.integers(0, V, n)
+            mus = rng.integers(0, 4, n).astype(np.int32)
+            t0 = time.perf_counter()
+            oracle.fat_grad_links(U_np, L, C_ASQTAD, GV_np, GW_np, sites, mus)
+            dt = time.perf_counter() - t0
+            if dt >= budget_s / 4:
+                break
+            n = int(n * max(2.0, budget_s / max(dt, 1e-3) * 0.9))
+        out["cpu_oracle"] = {"value": n / dt, "unit": "link-forces/s", "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": f"{n} random links, FP64 per-path algorithm ({dt:.1f} s)"}
+    return out
+
+
 def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
     """The FP64 oracle's force on a random sample of links of the same workload."""
     import numpy as np
@@ -200,6 +293,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-fat", action="store_true", help="skip the fat-link path force")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -220,7 +314,7 @@ def main():
     import paper_1808_02281_amd as sym
 
     if args.only_f32:
-        args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = True
+        args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = args.no_fat = True
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]
@@ -330,6 +424,15 @@ def main():
     if not args.no_batch:
         log("timing the 64-lattice batch")
         out["batch"] = bench_batch(sym, torch, gaugegen, u0, beta)
+
+    if not args.no_fat:
+        log("timing the fat-link path force")
+        del U32
+        if U64 is not None:
+            del U64
+        torch.cuda.empty_cache()
+        out["fat_path_force"] = bench_fat(sym, torch, U_np, L, args.steps, args.warmup, with_fp64=not args.no_fp64,
+                                          with_cpu=not args.no_cpu_baseline)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
