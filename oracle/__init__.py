@@ -1,6 +1,7 @@
 """FP64 CPU oracle for the one-loop Symanzik gauge action and force (arXiv:1808.02281, Sec. II)
-and for the asqtad / HISQ fat-link smearing and its path force (Secs. "Asqtad fermion",
-"HISQ fermion").
+for the asqtad / HISQ fat-link smearing and its path force (Secs. "Asqtad fermion",
+"HISQ fermion"), and for the Wilson-clover fermion matrix and its force at fixed X, Y
+(Sec. "Wilson fermion action with clover term").
 
 TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package. It shares no code with the GPU library
@@ -28,6 +29,12 @@ from .oracle import (  # noqa: F401
     fat_grad,
     fat_grad_links,
     fat_force_from_grad,
+    gamma,
+    clover_leaves,
+    wilson_apply,
+    wilson_psi,
+    wilson_force,
+    wilson_force_links,
     gell_mann,
     lie_derivative,
 )

@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "sym_oracle.c"), os.path.join(HERE, "fat_oracle.c")]
+SRCS = [os.path.join(HERE, "sym_oracle.c"), os.path.join(HERE, "fat_oracle.c"),
+        os.path.join(HERE, "wilson_oracle.c")]
 LIB = os.path.join(HERE, "libsymoracle.so")
 
 

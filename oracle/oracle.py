@@ -64,6 +64,19 @@ def _load():
     lib.orc_fat_grad_links.restype = None
     lib.orc_fat_force_from_grad.argtypes = [ctypes.c_int64, vp, vp, vp]
     lib.orc_fat_force_from_grad.restype = None
+    lib.orc_gamma.argtypes = [ctypes.c_int32, vp]
+    lib.orc_gamma.restype = None
+    lib.orc_clover_leaves.argtypes = [_c_int32_p, vp, vp]
+    lib.orc_clover_leaves.restype = None
+    lib.orc_wilson_apply.argtypes = [_c_int32_p, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.orc_wilson_apply.restype = None
+    lib.orc_wilson_psi.argtypes = [_c_int32_p, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.orc_wilson_psi.restype = ctypes.c_double
+    lib.orc_wilson_force.argtypes = [_c_int32_p, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
+    lib.orc_wilson_force.restype = None
+    lib.orc_wilson_force_links.argtypes = [_c_int32_p, ctypes.c_double, ctypes.c_double, vp, vp, vp, ctypes.c_int64,
+                                           _c_int64_p, _c_int32_p, vp]
+    lib.orc_wilson_force_links.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -251,6 +264,64 @@ def fat_force_from_grad(U, grad):
         raise ValueError("U and grad must have the same shape")
     G = np.empty_like(U)
     _load().orc_fat_force_from_grad(U.size // 9, U.ctypes.data, grad.ctypes.data, G.ctypes.data)
+    return G
+
+
+def _spinor(X, L):
+    X = np.ascontiguousarray(X, dtype=np.complex128)
+    Lx, Ly, Lz, Lt = L
+    if X.shape != (Lt, Lz, Ly, Lx, 4, 3):
+        raise ValueError(f"spinor shape {X.shape} does not match L={tuple(L)}")
+    return X
+
+
+def gamma(mu):
+    """Hermitian gamma matrix gamma_{mu+1} (DeGrand-Rossi basis), mu = 0..3 for x, y, z, t."""
+    g = np.empty((4, 4), dtype=np.complex128)
+    _load().orc_gamma(int(mu), g.ctypes.data)
+    return g
+
+
+def clover_leaves(U, L):
+    """Q_{n;mu nu} (eq. 17_7_20_8) for every site and ordered pair: shape (V, 4, 4, 3, 3)."""
+    U = _field(U, L)
+    V = int(np.prod(L))
+    Q = np.empty((V, 4, 4, 3, 3), dtype=np.complex128)
+    _load().orc_clover_leaves(_dims(L), U.ctypes.data, Q.ctypes.data)
+    return Q
+
+
+def wilson_apply(U, X, L, kappa, csw):
+    """D X for the Wilson matrix with clover term (eqs. 18_7_17_2, 18_7_17_4, 18_7_18_0)."""
+    U, X = _field(U, L), _spinor(X, L)
+    out = np.empty_like(X)
+    _load().orc_wilson_apply(_dims(L), float(kappa), float(csw), U.ctypes.data, X.ctypes.data, out.ctypes.data)
+    return out
+
+
+def wilson_psi(U, X, Y, L, kappa, csw):
+    """Psi = Y^+ D X + c.c. = 2 Re Y^+ D X."""
+    U, X, Y = _field(U, L), _spinor(X, L), _spinor(Y, L)
+    return _load().orc_wilson_psi(_dims(L), float(kappa), float(csw), U.ctypes.data, X.ctypes.data, Y.ctypes.data)
+
+
+def wilson_force(U, X, Y, L, kappa, csw):
+    """G with dPsi/domega^a = -2i tr(T_a G) on every link (eqs. 18_6_24_0, 18_1_29_20_1, 18_7_17_31)."""
+    U, X, Y = _field(U, L), _spinor(X, L), _spinor(Y, L)
+    G = np.empty_like(U)
+    _load().orc_wilson_force(_dims(L), float(kappa), float(csw), U.ctypes.data, X.ctypes.data, Y.ctypes.data,
+                             G.ctypes.data)
+    return G
+
+
+def wilson_force_links(U, X, Y, L, kappa, csw, sites, mus):
+    U, X, Y = _field(U, L), _spinor(X, L), _spinor(Y, L)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    G = np.empty((len(sites), 3, 3), dtype=np.complex128)
+    _load().orc_wilson_force_links(_dims(L), float(kappa), float(csw), U.ctypes.data, X.ctypes.data,
+                                   Y.ctypes.data, len(sites), sites.ctypes.data_as(_c_int64_p),
+                                   mus.ctypes.data_as(_c_int32_p), G.ctypes.data)
     return G
 
 
