@@ -182,6 +182,32 @@ int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U
 int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U, const void* GV, const void* GW,
                   void* out, int mode, void* ws, size_t ws_bytes, sym_stream_t stream);
 
+/*
+ * Wilson fermion force with clover term for given vectors X, Y (Sec. "Wilson fermion
+ * action with clover term"): D = A - kappa Dh (eq. 18_7_17_2) with the hopping part of
+ * eq. 18_7_17_4, (1 - gamma_mu) U_{n,mu} forwards and (1 + gamma_mu) U_{n,-mu} backwards,
+ * and the clover diagonal A_n = 1 - (c_sw kappa/16) sum_{mu != nu} [gamma_mu, gamma_nu]
+ * Q_{n;mu nu} (eq. 18_7_18_0, kappa = 1/(2(m+4)); Q the clover leaves of eq. 17_7_20_8).
+ * Gamma matrices are Hermitian in the DeGrand-Rossi basis, gamma_1..4 along x, y, z, t.
+ *
+ * sym_wilson_force writes, for every link, G = -(1/2) M_TA where
+ * dPsi/domega^a = Re tr(i T_a M) = -2i tr(T_a G) for Psi(U) = Y^+ D X + c.c. (the
+ * derivative of eq. 18_6_24_0; X = (D^+ D)^{-1} phi and Y = D X in an HMC, any fixed
+ * vectors here). G is traceless antihermitian in the convention of sym_force; the
+ * pseudofermion action at fixed X, Y changes by -dPsi, so its force is -G.
+ * kappa, c_sw: finite. U: link field; X, Y: spinor fields (read); G: link layout (out).
+ * ws: at least sym_wilson_workspace_bytes(L, prec) bytes (6 colour matrices per site).
+ *
+ * Spinor layout: field[p][3*spin + colour][V/2] complex (T re, T im), parity p and
+ * checkerboard index as for links; sym_pack_spinor / sym_unpack_spinor convert from / to
+ * the canonical complex array (Lt,Lz,Ly,Lx,4,3).
+ */
+size_t sym_wilson_workspace_bytes(const int32_t L[4], int prec);
+int sym_wilson_force(const int32_t L[4], int prec, double kappa, double csw, const void* U, const void* X,
+                     const void* Y, void* G, void* ws, size_t ws_bytes, sym_stream_t stream);
+int sym_pack_spinor(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
+int sym_unpack_spinor(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);
+
 /* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);

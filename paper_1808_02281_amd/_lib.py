@@ -36,6 +36,10 @@ EXPORTS = (
     "sym_fat_workspace_bytes",
     "sym_fat_links",
     "sym_fat_force",
+    "sym_wilson_workspace_bytes",
+    "sym_wilson_force",
+    "sym_pack_spinor",
+    "sym_unpack_spinor",
 )
 FAT_MODES = {"grad": 0, "force": 1}
 
@@ -102,6 +106,15 @@ def lib():
     L.sym_fat_links.restype = ctypes.c_int
     L.sym_fat_force.argtypes = [i32p, ctypes.c_int, dp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.sym_fat_force.restype = ctypes.c_int
+    L.sym_wilson_workspace_bytes.argtypes = [i32p, ctypes.c_int]
+    L.sym_wilson_workspace_bytes.restype = ctypes.c_size_t
+    L.sym_wilson_force.argtypes = [i32p, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp,
+                                   ctypes.c_size_t, vp]
+    L.sym_wilson_force.restype = ctypes.c_int
+    L.sym_pack_spinor.argtypes = [i32p, ctypes.c_int, vp, vp, vp]
+    L.sym_pack_spinor.restype = ctypes.c_int
+    L.sym_unpack_spinor.argtypes = [i32p, ctypes.c_int, vp, vp, vp]
+    L.sym_unpack_spinor.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -323,3 +323,75 @@ def fat_force(U, L, c, GV, GW=None, mode="grad", out=None):
                                                          _lib.FAT_MODES[mode], _ptr(ws), ws.numel(),
                                                          _stream(U.device)))
     return o
+
+
+# ----------------------------------------------------------- Wilson-clover force
+
+def spinor_shape(L):
+    """Shape of a spinor field in the SoA even-odd layout: (2, 12, V/2, 2) reals."""
+    return (2, 12, volume(L) // 2, 2)
+
+
+def _check_spinor(name, t, L):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA (HIP) tensor")
+    if tuple(t.shape) != spinor_shape(L):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {spinor_shape(L)} for L={tuple(L)}")
+    prec_of(t.dtype)
+
+
+def pack_spinor(aos, L):
+    """Canonical complex (Lt,Lz,Ly,Lx,4,3) CUDA tensor -> SoA even-odd spinor field."""
+    if not aos.is_cuda or not aos.is_contiguous():
+        raise ValueError("aos must be a contiguous CUDA tensor")
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    if tuple(aos.shape) != (Lt, Lz, Ly, Lx, 4, 3):
+        raise ValueError(f"aos shape {tuple(aos.shape)} does not match L={tuple(L)}")
+    real = {torch.complex64: torch.float32, torch.complex128: torch.float64}.get(aos.dtype)
+    if real is None:
+        raise TypeError("aos must be complex64 or complex128")
+    out = torch.empty(spinor_shape(L), dtype=real, device=aos.device)
+    _lib.check("sym_pack_spinor", _lib.lib().sym_pack_spinor(_lib.dims(L), prec_of(real), _ptr(aos), _ptr(out),
+                                                             _stream(aos.device)))
+    return out
+
+
+def unpack_spinor(soa, L):
+    """SoA even-odd spinor field -> canonical complex (Lt,Lz,Ly,Lx,4,3) tensor."""
+    _check_spinor("soa", soa, L)
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    cdt = torch.complex64 if soa.dtype == torch.float32 else torch.complex128
+    out = torch.empty((Lt, Lz, Ly, Lx, 4, 3), dtype=cdt, device=soa.device)
+    _lib.check("sym_unpack_spinor", _lib.lib().sym_unpack_spinor(_lib.dims(L), prec_of(soa.dtype), _ptr(soa),
+                                                                 _ptr(out), _stream(soa.device)))
+    return out
+
+
+def wilson_workspace(L, prec, device):
+    device = torch.device(device)
+    key = ("wilson", device.index, tuple(int(v) for v in L), int(prec))
+    ws = _WS_CACHE.get(key)
+    if ws is None:
+        n = int(_lib.lib().sym_wilson_workspace_bytes(_lib.dims(L), int(prec)))
+        if n == 0:
+            raise ValueError(f"invalid lattice {tuple(L)} or precision {prec}")
+        ws = torch.empty(n, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = ws
+    return ws
+
+
+def wilson_force(U, X, Y, L, kappa, csw, out=None):
+    """G with dPsi/domega^a = -2i tr(T_a G), Psi = Y^+ D X + c.c. (sym_wilson_force)."""
+    _check_field("U", U, L)
+    _check_spinor("X", X, L)
+    _check_spinor("Y", Y, L)
+    if X.dtype != U.dtype or Y.dtype != U.dtype:
+        raise TypeError("X and Y must have the dtype of U")
+    prec = prec_of(U.dtype)
+    ws = wilson_workspace(L, prec, U.device)
+    G = torch.empty_like(U) if out is None else out
+    _check_field("out", G, L)
+    _lib.check("sym_wilson_force", _lib.lib().sym_wilson_force(_lib.dims(L), prec, float(kappa), float(csw), _ptr(U),
+                                                               _ptr(X), _ptr(Y), _ptr(G), _ptr(ws), ws.numel(),
+                                                               _stream(U.device)))
+    return G

@@ -35,6 +35,7 @@ UNITS = [
     ("force_batch.hip", ["-DSYM_ONLY_F64"], "force_batch_f64.o"),
     ("fat.hip", ["-DSYM_ONLY_F32"], "fat_f32.o"),
     ("fat.hip", ["-DSYM_ONLY_F64"], "fat_f64.o"),
+    ("wilson.hip", [], "wilson.o"),
 ]
 
 

@@ -387,6 +387,11 @@ int do_fat_force(const Geom& g, const sym::fat::FatCoeffs& c, const void* U, con
   return hip_status(e);
 }
 
+size_t wilson_ws(const Geom& g, int prec) {
+  const size_t cxb = prec == SYM_F64 ? 2 * sizeof(double) : 2 * sizeof(float);
+  return align256((size_t)2 * 6 * 9 * cxb * (size_t)g.Vh);
+}
+
 }  // namespace
 
 extern "C" {
@@ -599,6 +604,74 @@ int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return prec == SYM_F64 ? do_fat_force<double>(g, cf, U, GV, GW, out, mode, fat_carve<double>(ws, g, prec), s)
                          : do_fat_force<float>(g, cf, U, GV, GW, out, mode, fat_carve<float>(ws, g, prec), s);
+}
+
+size_t sym_wilson_workspace_bytes(const int32_t L[4], int prec) {
+  Geom g;
+  if (make_geom(L, &g) != SYM_OK || check_prec(prec) != SYM_OK) return 0;
+  return wilson_ws(g, prec);
+}
+
+int sym_wilson_force(const int32_t L[4], int prec, double kappa, double csw, const void* U, const void* X,
+                     const void* Y, void* G, void* ws, size_t ws_bytes, sym_stream_t stream) {
+  Geom g;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = check_ptr(U)) || (rc = check_ptr(X)) ||
+      (rc = check_ptr(Y)) || (rc = check_ptr(G)) || (rc = check_ptr(ws)))
+    return rc;
+  if (!isfinite(kappa) || !isfinite(csw)) return SYM_EINVAL;
+  if (ws_bytes < wilson_ws(g, prec)) return SYM_EWORKSPACE;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (prec == SYM_F64) {
+    double* K = static_cast<double*>(ws);
+    e = timed("wilson_clover", s, [&] {
+      return sym::launch_wilson_clover<double>(g, static_cast<const double*>(X), static_cast<const double*>(Y), K, s);
+    });
+    if (e == hipSuccess)
+      e = timed("wilson_force", s, [&] {
+        return sym::launch_wilson_force<double>(g, static_cast<const double*>(U), static_cast<const double*>(X),
+                                                static_cast<const double*>(Y), K, static_cast<double*>(G), kappa, csw,
+                                                s);
+      });
+  } else {
+    float* K = static_cast<float*>(ws);
+    e = timed("wilson_clover", s, [&] {
+      return sym::launch_wilson_clover<float>(g, static_cast<const float*>(X), static_cast<const float*>(Y), K, s);
+    });
+    if (e == hipSuccess)
+      e = timed("wilson_force", s, [&] {
+        return sym::launch_wilson_force<float>(g, static_cast<const float*>(U), static_cast<const float*>(X),
+                                               static_cast<const float*>(Y), K, static_cast<float*>(G), kappa, csw, s);
+      });
+  }
+  return hip_status(e);
+}
+
+int sym_pack_spinor(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream) {
+  Geom g;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = check_ptr(aos_lex)) || (rc = check_ptr(soa)))
+    return rc;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e =
+      prec == SYM_F64
+          ? sym::launch_spinor_layout<double>(g, static_cast<const double*>(aos_lex), static_cast<double*>(soa), true, s)
+          : sym::launch_spinor_layout<float>(g, static_cast<const float*>(aos_lex), static_cast<float*>(soa), true, s);
+  return hip_status(e);
+}
+
+int sym_unpack_spinor(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream) {
+  Geom g;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = check_ptr(soa)) || (rc = check_ptr(aos_lex)))
+    return rc;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e =
+      prec == SYM_F64
+          ? sym::launch_spinor_layout<double>(g, static_cast<const double*>(soa), static_cast<double*>(aos_lex), false, s)
+          : sym::launch_spinor_layout<float>(g, static_cast<const float*>(soa), static_cast<float*>(aos_lex), false, s);
+  return hip_status(e);
 }
 
 int sym_set_coeffs_override(const double c[3]) {

@@ -115,4 +115,14 @@ hipError_t launch_pack(const Geom& g, const T* aos, T* soa, hipStream_t s);
 template <typename T>
 hipError_t launch_unpack(const Geom& g, const T* soa, T* aos, hipStream_t s);
 
+// Wilson fermion force with clover term (wilson.hip): clover insertions K (6 colour
+// matrices per site) from X, Y; per-link force; spinor layout conversion.
+template <typename T>
+hipError_t launch_wilson_clover(const Geom& g, const T* X, const T* Y, T* K, hipStream_t s);
+template <typename T>
+hipError_t launch_wilson_force(const Geom& g, const T* U, const T* X, const T* Y, const T* K, T* out, double kappa,
+                               double csw, hipStream_t s);
+template <typename T>
+hipError_t launch_spinor_layout(const Geom& g, const T* src, T* dst, bool pack, hipStream_t s);
+
 }  // namespace sym

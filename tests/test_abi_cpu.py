@@ -144,3 +144,17 @@ def test_fat_validation(L_):
     assert ff(ok, 1, c, FAKE, FAKE, None, None, 0, FAKE, HUGE, None) == -2   # out required
     assert ff(ok, 3, c, FAKE, FAKE, None, FAKE, 0, FAKE, HUGE, None) == -1
     assert ff(ok, 2, c, FAKE, FAKE, FAKE, FAKE, 1, FAKE, 8, None) == -3
+
+
+def test_wilson_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    assert L_.sym_wilson_workspace_bytes(ok, 1) >= 2 * 6 * 9 * 128 * 8
+    assert L_.sym_wilson_workspace_bytes(_dims(4, 4, 5, 4), 1) == 0
+    w = L_.sym_wilson_force
+    assert w(ok, 1, math.nan, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, HUGE, None) == -1
+    assert w(ok, 1, 0.12, math.inf, FAKE, FAKE, FAKE, FAKE, FAKE, HUGE, None) == -1
+    assert w(ok, 1, 0.12, 1.0, FAKE, None, FAKE, FAKE, FAKE, HUGE, None) == -2
+    assert w(ok, 1, 0.12, 1.0, FAKE, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
+    assert w(ok, 1, 0.12, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, 16, None) == -3
+    assert L_.sym_pack_spinor(_dims(4, 4, 4, 3), 1, FAKE, FAKE, None) == -1
+    assert L_.sym_unpack_spinor(ok, 1, None, FAKE, None) == -2
