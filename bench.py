@@ -44,6 +44,14 @@ FAT_FLOP = {"fat_fk1": 2592, "fat_fk2": 6102, "fat_fk3": 3348, "fat_bk3": 2700, 
 FAT_MATRICES = {"fat_fk1": 7, "fat_fk2": 10, "fat_fk3": 12, "fat_bk3": 8, "fat_bk2": 10, "fat_gk": 22}
 C_ASQTAD = (5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
 
+# Wilson-clover force, flop per link (force kernel: 6 clover plaquettes of 9 products
+# each with the insertions, hopping outer products, U B' and C' U^+, TA) and per link of
+# the clover-insertion pass (6 colour matrices per site from X, Y); minimum bytes per
+# link in reals: force = U + G + a quarter of the site's X, Y (24 complex) and K (54 complex).
+WILSON_FLOP = {"wilson_force": 12450, "wilson_clover": 500}
+WILSON_REALS = {"wilson_force": 18 + 18 + (48 + 108) / 4, "wilson_clover": (48 + 108) / 4}
+KAPPA, CSW = 0.1242, 1.37
+
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts packed FMA)
 PEAK_F32_NONPACKED = 78.6e12               # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_HBM = 8.0e12
@@ -246,6 +254,75 @@ def bench_fat(sym, torch, U_np, L, steps, warmup, with_fp64=True, with_cpu=True,
     return out
 
 
+def bench_wilson(sym, torch, U_np, L, steps, warmup, with_fp64=True, with_cpu=True, budget_s=6.0):
+    """Wilson-clover fermion force on the same lattice for synthetic X, Y (complex Gaussian
+    spinors, seeds 8 and 9; kappa 0.1242, c_sw 1.37); one step = sym_wilson_force."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    V = int(np.prod(L))
+    links = 4 * V
+    rng = np.random.default_rng(8)
+    shape = (L[3], L[2], L[1], L[0], 4, 3)
+    X_np = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+    rng = np.random.default_rng(9)
+    Y_np = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+    out = {"workload": f"{WORKLOAD}, X and Y complex Gaussian spinors (seeds 8, 9)", "kappa": KAPPA, "csw": CSW}
+    for prec, cdt in (("f32", torch.complex64), ("f64", torch.complex128)):
+        if prec == "f64" and not with_fp64:
+            continue
+        U = sym.pack(torch.from_numpy(U_np).to(dev).to(cdt), L)
+        X = sym.pack_spinor(torch.from_numpy(X_np).to(dev).to(cdt), L)
+        Y = sym.pack_spinor(torch.from_numpy(Y_np).to(dev).to(cdt), L)
+        G = torch.empty_like(U)
+        for _ in range(warmup):
+            sym.wilson_force(U, X, Y, L, KAPPA, CSW, out=G)
+        torch.cuda.synchronize()
+        sym.profile_enable(True)
+        sym.profile_collect()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            sym.wilson_force(U, X, Y, L, KAPPA, CSW, out=G)
+        e1.record()
+        torch.cuda.synchronize()
+        kern = sym.profile_collect()
+        sym.profile_enable(False)
+        ms = e0.elapsed_time(e1) / steps
+        r = 4 if prec == "f32" else 8
+        per = {}
+        for name, (tot, n) in kern.items():
+            t = tot / n * 1e-3
+            per[name] = {"ms": t * 1e3, "tflops": WILSON_FLOP[name] * links / t / 1e12,
+                         "min_hbm_tbs": WILSON_REALS[name] * r * links / t / 1e12}
+        fk = per["wilson_force"]
+        peak = PEAK[prec]
+        out[prec] = {"value": links / (ms * 1e-3), "unit": "link-forces/s", "ms_per_step": ms, "kernels": per,
+                     "roofline": {"kernel": "wilson_force", "bound": "alu", "achieved": fk["tflops"],
+                                  "peak": peak / 1e12, "unit": "TFLOP/s", "frac": fk["tflops"] * 1e12 / peak,
+                                  "flop_per_link": WILSON_FLOP["wilson_force"],
+                                  "hbm_min_bytes_per_link": WILSON_REALS["wilson_force"] * r,
+                                  "hbm_frac_at_min_bytes": fk["min_hbm_tbs"] * 1e12 / PEAK_HBM}}
+        log(f"  wilson force {prec}: {ms:.3f} ms/step; {per}")
+        del U, X, Y, G
+    if with_cpu:
+        import oracle
+
+        n = 256
+        while True:
+            sites = rng.integers(0, V, n)
+            mus = rng.integers(0, 4, n).astype(np.int32)
+            t0 = time.perf_counter()
+            oracle.wilson_force_links(U_np, X_np, Y_np, L, KAPPA, CSW, sites, mus)
+            dt = time.perf_counter() - t0
+            if dt >= budget_s / 4:
+                break
+            n = int(n * max(2.0, budget_s / max(dt, 1e-3) * 0.9))
+        out["cpu_oracle"] = {"value": n / dt, "unit": "link-forces/s", "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": f"{n} random links, FP64 ({dt:.1f} s)"}
+    return out
+
+
 def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
     """The FP64 oracle's force on a random sample of links of the same workload."""
     import numpy as np
@@ -294,6 +371,7 @@ def main():
     ap.add_argument("--no-md", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fat", action="store_true", help="skip the fat-link path force")
+    ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-clover force")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -315,6 +393,7 @@ def main():
 
     if args.only_f32:
         args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = args.no_fat = True
+        args.no_wilson = True
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]
@@ -433,6 +512,11 @@ def main():
         torch.cuda.empty_cache()
         out["fat_path_force"] = bench_fat(sym, torch, U_np, L, args.steps, args.warmup, with_fp64=not args.no_fp64,
                                           with_cpu=not args.no_cpu_baseline)
+
+    if not args.no_wilson:
+        log("timing the Wilson-clover force")
+        out["wilson_clover_force"] = bench_wilson(sym, torch, U_np, L, args.steps, args.warmup,
+                                                  with_fp64=not args.no_fp64, with_cpu=not args.no_cpu_baseline)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
