@@ -336,7 +336,7 @@ size_t link_field_bytes(const Geom& g, int prec) {
   return (size_t)8 * 9 * 2 * real * (size_t)g.Vh;  // 4 directions x 2 parities x 9 complex
 }
 
-size_t fat_ws_bytes(const Geom& g, int prec) { return 18 * align256(link_field_bytes(g, prec)); }
+size_t fat_ws_bytes(const Geom& g, int prec) { return sym::fat::kFatFields * align256(link_field_bytes(g, prec)); }
 
 template <typename T>
 sym::fat::Fields<T> fat_carve(void* ws, const Geom& g, int prec) {
@@ -344,9 +344,12 @@ sym::fat::Fields<T> fat_carve(void* ws, const Geom& g, int prec) {
   char* p = static_cast<char*>(ws);
   sym::fat::Fields<T> w;
   w.T1 = reinterpret_cast<T*>(p);
-  w.midc = reinterpret_cast<T*>(p + 6 * one);
-  w.gM = reinterpret_cast<T*>(p + 9 * one);
-  w.ginner = reinterpret_cast<T*>(p + 15 * one);
+  w.inner = reinterpret_cast<T*>(p + 6 * one);
+  w.M = reinterpret_cast<T*>(p + 9 * one);
+  w.gM = reinterpret_cast<T*>(p + 15 * one);
+  w.gmid = reinterpret_cast<T*>(p + 21 * one);
+  w.gT1 = reinterpret_cast<T*>(p + 24 * one);
+  w.D = reinterpret_cast<T*>(p + 30 * one);
   return w;
 }
 

@@ -11,84 +11,80 @@ using fat::Fields;
 namespace {
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void fat_fk1_kernel(Geom g, const T* __restrict__ U, T* __restrict__ T1,
+__global__ __launch_bounds__(kBlock) void fat_fk1_kernel(Geom g, const T* __restrict__ U, Fields<T> w, FatCoeffs cf,
                                                           int ntiles) {
   const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
   const int cb = lt.chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  fat::fk1_step<1>(c, T1, cb);
+  fat::fk1_step<1>(c, w, T(cf.c[2]), T(cf.c[3]), cb);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ T1,
-                                                          T* __restrict__ midc, FatCoeffs cf, int ntiles) {
+__global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __restrict__ U, Fields<T> w, FatCoeffs cf,
+                                                          int ntiles) {
   const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
   const int cb = lt.chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  fat::fk2_step<1>(c, T1, midc, cf, cb);
+  fat::fk2_step<1>(c, w, cf, cb);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void fat_fk3_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ T1,
-                                                          const T* __restrict__ midc, T* __restrict__ V,
-                                                          T* __restrict__ W, FatCoeffs cf, int ntiles) {
+__global__ __launch_bounds__(kBlock) void fat_fk3_kernel(Geom g, const T* __restrict__ U, Fields<T> w,
+                                                          T* __restrict__ V, T* __restrict__ W, FatCoeffs cf,
+                                                          int ntiles) {
   const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
   const int cb = lt.chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  const su3<T> u = c.template u<0, 0, 0, 0, 0>();
-  su3<T> acc = u;
-  const T c1 = T(cf.c[0]);
-#pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    acc.e[e].re *= c1;
-    acc.e[e].im *= c1;
-  }
-  fat::fk3_step<1>(acc, c, T1, midc, T(cf.c[4]));
+  su3<T> acc = c.template u<0, 0, 0, 0, 0>();
+  fat::scale(acc, T(cf.c[0]));
+  fat::fk3_step<1>(acc, c, w);
   store_link(block_ptr(V, lt.mu, lt.p, g.Vh), g.Vh, cb, acc);
   if (W != nullptr) {
     fat::launder(c);
-    su3<T> w = mul<false, false>(c.template u<0, 0, 0, 0, 0>(), c.template u<1, 0, 0, 0, 0>());
-    w = mul<false, false>(w, c.template u<2, 0, 0, 0, 0>());
-    const T cN = T(cf.c[5]);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      w.e[e].re *= cN;
-      w.e[e].im *= cN;
-    }
-    store_link(block_ptr(W, lt.mu, lt.p, g.Vh), g.Vh, cb, w);
+    su3<T> nk = mul<false, false>(c.template u<0, 0, 0, 0, 0>(), c.template u<1, 0, 0, 0, 0>());
+    nk = mul<false, false>(nk, c.template u<2, 0, 0, 0, 0>());
+    fat::scale(nk, T(cf.c[5]));
+    store_link(block_ptr(W, lt.mu, lt.p, g.Vh), g.Vh, cb, nk);
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void fat_bk3_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ GV,
-                                                          T* __restrict__ gM, int ntiles) {
+                                                          Fields<T> w, int ntiles) {
   const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
   const int cb = lt.chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  fat::bk3_step<1>(c, GV, gM, cb);
+  fat::bk3_step<1>(c, GV, w, cb);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ gM,
-                                                          T* __restrict__ ginner, int ntiles) {
+__global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ GV,
+                                                          Fields<T> w, FatCoeffs cf, int ntiles) {
   const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
   const int cb = lt.chunk * kBlock + threadIdx.x;
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  fat::bk2_step<1>(c, gM, ginner, cb);
+  // D = c1 GV + c3 sum_k gmid_k + c5 sum_m g_inner_m
+  su3<T> dsum = c.template f<0, 0, 0, 0, 0>(GV, 1, 0);
+  fat::scale(dsum, T(cf.c[0]));
+  for (int k = 0; k < 3; ++k) axpy(dsum, T(cf.c[1]), c.template f<0, 0, 0, 0, 0>(w.gmid, 3, k));
+  SYM_FAT_FENCE();
+  fat::bk2_step<1>(c, w, cf, dsum, cb);
+  fat::store_slot(w.D, 1, 0, lt.mu, lt.p, g.Vh, cb, dsum);
 }
 
-// Gradient (or force) of the thin link (y, nu): direct terms, transports of U_nu's own
-// chain, Naik terms, and the deposits of the transports along nu of the other chains.
+// Gradient (or force) of the thin link (y, nu): the direct terms D, the transports of
+// U_nu's own chain, the Naik terms, and the deposits of the transports along nu of the
+// other chains.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restrict__ U, const T* __restrict__ GV,
                                                          const T* __restrict__ GW, Fields<T> w, T* __restrict__ out,
@@ -98,19 +94,10 @@ __global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restr
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  const T c1 = T(cf.c[0]), c3 = T(cf.c[1]), c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]), cN = T(cf.c[5]);
 
-  // direct terms: c1 GV + c3 sum gmid + c5 sum g_inner (all at y, direction nu)
-  su3<T> acc = c.template f<0, 0, 0, 0, 0>(GV, 1, 0);
-#pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    acc.e[e].re *= c1;
-    acc.e[e].im *= c1;
-  }
-  for (int j = 0; j < 6; ++j) axpy(acc, c3, c.template f<0, 0, 0, 0, 0>(w.gM, 6, j));
-  for (int j = 0; j < 3; ++j) axpy(acc, c5, c.template f<0, 0, 0, 0, 0>(w.ginner, 3, j));
+  su3<T> acc = c.template f<0, 0, 0, 0, 0>(w.D, 1, 0);
   SYM_FAT_FENCE();
-  fat::gk_pull<1>(acc, c, w, c7, cL);
+  fat::gk_pull<1>(acc, c, w);
 
   if (GW != nullptr) {
     // W_{y-k nu} = cN U_{y-k nu,nu} U_{y-(k-1)nu,nu} U_{y-(k-2)nu,nu} for k = 0, 1, 2
@@ -124,11 +111,11 @@ __global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restr
     mac<false, true>(nk, t, u1);
     t = mul<true, true>(um1, cc.template u<-2, 0, 0, 0, 0>());
     mac<false, false>(nk, t, cc.template f<-2, 0, 0, 0, 0>(GW, 1, 0));
-    axpy(acc, cN, nk);
+    axpy(acc, T(cf.c[5]), nk);
     SYM_FAT_FENCE();
   }
 
-  fat::gk_factor<1>(acc, c, GV, w, cf);
+  fat::gk_factor<1>(acc, c, GV, w);
 
   fat::launder(c);
   cx<T>* dst = block_ptr(out, lt.mu, lt.p, g.Vh);
@@ -147,7 +134,7 @@ template <typename T>
 hipError_t launch_fat_fk3(const Geom& g, const T* U, T* V, T* W, const FatCoeffs& c, const Fields<T>& w,
                           hipStream_t s) {
   const int nt = link_tiles(g);
-  fat_fk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, w.midc, V, W, c, nt);
+  fat_fk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w, V, W, c, nt);
   return hipGetLastError();
 }
 
@@ -157,16 +144,16 @@ hipError_t launch_fat_stage(int stage, const Geom& g, const T* U, const T* GV, c
   const int nt = link_tiles(g);
   switch (stage) {
     case 0:
-      fat_fk1_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, nt);
+      fat_fk1_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w, c, nt);
       break;
     case 1:
-      fat_fk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.T1, w.midc, c, nt);
+      fat_fk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w, c, nt);
       break;
     case 2:
-      fat_bk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, GV, w.gM, nt);
+      fat_bk3_kernel<T><<<nt, kBlock, 0, s>>>(g, U, GV, w, nt);
       break;
     case 3:
-      fat_bk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, w.gM, w.ginner, nt);
+      fat_bk2_kernel<T><<<nt, kBlock, 0, s>>>(g, U, GV, w, c, nt);
       break;
     default:
       if (mode == 0)

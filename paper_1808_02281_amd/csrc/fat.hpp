@@ -16,7 +16,8 @@
 //   V_mu = c1 U_mu + sum_{nu, s} Sts_nu( midc_nu + cL T1_{nu,s} ),
 //   midc_nu = c3 U_mu + sum_{rho != nu} sum_s Sts_rho( c5 U_mu + c7 (T1_{sigma,+} + T1_{sigma,-}) ),
 //   T1_{sigma,s} = Sts_sigma(U_mu),   sigma the axis other than mu, nu, rho.
-// Pass FK1 writes T1 (6 per link), FK2 midc (3 per link), FK3 V and the Naik link
+// Pass FK1 writes T1 and the combinations inner = c5 U + c7 (T1_+ + T1_-), FK2 writes
+// M_{nu,s} = midc_nu + cL T1_{nu,s}, FK3 V and the Naik link
 // W = cN U_{x,mu} U_{x+mu,mu} U_{x+2mu,mu}: 12 + 24 + 14 products per link, against
 // 505 link positions over the 86 paths.
 //
@@ -32,8 +33,9 @@
 // Everything is a gather: each thread owns its output, no atomics.
 //
 // Intermediate fields (workspace), per direction mu and parity, "slot fields"
-//   X[mu][p][slot][9][V/2] complex:  T1 6 slots (slot 2k + (s<0), k = index of sigma
-//   among the axes other than mu, ascending), midc 3, gM 6, g_inner 3.
+//   X[mu][p][slot][9][V/2] complex: see struct Fields. Every linear combination a later
+//   pass reads at several neighbours is stored once, so each transport loads one matrix
+//   besides its two links.
 #pragma once
 
 #include "kernels.hpp"
@@ -204,14 +206,68 @@ __device__ __forceinline__ void factor_acc(su3<T>& acc, const Ctx<T>& c, const C
   }
 }
 
-// Workspace fields of one lattice (slot fields, see the header comment).
+// One matrix field (slot `slot` of a field with `nslot` matrices per link) on the links
+// of direction ax[A]; the U field itself.
+template <typename T>
+struct One {
+  const T* F[3];  // F[0] used; the array keeps the interface of Comb for fresh()
+  int nslot;
+  int slot;
+
+  template <int D0, int D1, int D2, int D3, int A>
+  __device__ __forceinline__ su3<T> at(const Ctx<T>& c) const {
+    return c.template f<D0, D1, D2, D3, A>(F[0], nslot, slot);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ One<T> one(const T* F, int nslot, int slot) {
+  One<T> o;
+  o.F[0] = F;
+  o.F[1] = nullptr;
+  o.F[2] = nullptr;
+  o.nslot = nslot;
+  o.slot = slot;
+  return o;
+}
+
+template <typename T>
+struct UOnly {
+  const T* F[3];  // unused
+
+  template <int D0, int D1, int D2, int D3, int A>
+  __device__ __forceinline__ su3<T> at(const Ctx<T>& c) const {
+    return c.template u<D0, D1, D2, D3, A>();
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ UOnly<T> u_only() {
+  UOnly<T> o;
+  o.F[0] = o.F[1] = o.F[2] = nullptr;
+  return o;
+}
+
+// Workspace fields of one lattice (slot fields X[mu][p][slot][9][V/2]):
+//   T1[2k + (s<0)] = Sts_{a_k}(U_mu)                       (6 slots, pass FK1)
+//   inner[m] = c5 U_mu + c7 (T1[2m] + T1[2m+1])             (3 slots, FK1)
+//   M[2k + (s<0)] = midc_k + cL T1[2k + (s<0)]              (6 slots, FK2)
+//   gM[2k + (s<0)] = St-s_{a_k}(GV_mu)                      (6 slots, BK3)
+//   gmid[k] = gM[2k] + gM[2k+1]                             (3 slots, BK3)
+//   gT1[2m + (s<0)] = c7 g_inner_m + cL gM[2m + (s<0)]      (6 slots, BK2)
+//   D = c1 GV + c3 sum_k gmid_k + c5 sum_m g_inner_m        (1 slot,  BK2)
+// with a_k the k-th axis other than mu (ascending). 31 matrices per link.
 template <typename T>
 struct Fields {
-  T* T1;     // 6 slots
-  T* midc;   // 3 slots
-  T* gM;     // 6 slots
-  T* ginner; // 3 slots
+  T* T1;
+  T* inner;
+  T* M;
+  T* gM;
+  T* gmid;
+  T* gT1;
+  T* D;
 };
+constexpr int kFatFields = 31;
 
 struct FatCoeffs {
   double c[6];  // c1, c3, c5, c7, cL, cN
@@ -223,218 +279,216 @@ __device__ __forceinline__ void store_slot(T* F, int nslot, int slot, int dir, i
   store_link(blk, Vh, cb, m);
 }
 
-// ------------------------------------------------------------------ forward
-
-// FK1: T1[mu][2(K-1) + (S<0)] = St^S_{ax[K]}(U_mu)
-template <int K, typename T>
-__device__ __forceinline__ void fk1_step(const Ctx<T>& c0, T* T1, int cb) {
-  if constexpr (K <= 3) {
-    Ctx<T> c = c0;
-    launder(c);
-    const auto A = comb_u<T>(T(1));
-    su3<T> r;
-    set_zero(r);
-    st_acc<K, 1>(r, c, A);
-    store_slot(T1, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
-    SYM_FAT_FENCE();
-    set_zero(r);
-    st_acc<K, -1>(r, c, A);
-    store_slot(T1, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
-    SYM_FAT_FENCE();
-    fk1_step<K + 1>(c0, T1, cb);
+template <typename T>
+__device__ __forceinline__ void scale(su3<T>& a, T s) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    a.e[e].re *= s;
+    a.e[e].im *= s;
   }
 }
 
-// FK2, one output: midc[mu][K-1] = c3 U_mu + sum_{J != K} sum_s Sts_{ax[J]}(c5 U_mu + c7 (T1_{M,+} + T1_{M,-}))
+// ------------------------------------------------------------------ forward
+
+// FK1: T1 = Sts_{ax[K]}(U_mu) and inner[K-1] = c5 U + c7 (T1_{K,+} + T1_{K,-})
+template <int K, typename T>
+__device__ __forceinline__ void fk1_step(const Ctx<T>& c0, const Fields<T>& w, T c5, T c7, int cb) {
+  if constexpr (K <= 3) {
+    Ctx<T> c = c0;
+    launder(c);
+    const auto A = u_only<T>();
+    su3<T> r;
+    set_zero(r);
+    st_acc<K, 1>(r, c, A);
+    store_slot(w.T1, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
+    su3<T> in = c.template u<0, 0, 0, 0, 0>();
+    scale(in, c5);
+    axpy(in, c7, r);
+    SYM_FAT_FENCE();
+    set_zero(r);
+    st_acc<K, -1>(r, c, A);
+    store_slot(w.T1, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
+    axpy(in, c7, r);
+    store_slot(w.inner, 3, K - 1, c.ax[0], c.p, c.Vh, cb, in);
+    SYM_FAT_FENCE();
+    fk1_step<K + 1>(c0, w, c5, c7, cb);
+  }
+}
+
+// FK2: midc_K = c3 U_mu + sum_{J != K} sum_s Sts_{ax[J]}(inner[M]), M the third axis;
+// stores M[K, s] = midc_K + cL T1[K, s]
 template <int K, int J, typename T>
-__device__ __forceinline__ void fk2_inner(su3<T>& acc, const Ctx<T>& c0, const T* T1, T c5, T c7) {
+__device__ __forceinline__ void fk2_inner(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
   if constexpr (J <= 3) {
     if constexpr (J != K) {
       Ctx<T> c = c0;
       launder(c);
       constexpr int M = 6 - K - J;
-      auto A = comb_u<T>(c5);
-      comb_add(A, T1, 6, 2 * (M - 1), c7);
-      comb_add(A, T1, 6, 2 * (M - 1) + 1, c7);
+      const auto A = one(static_cast<const T*>(w.inner), 3, M - 1);
       st_acc<J, 1>(acc, c, A);
       SYM_FAT_FENCE();
       st_acc<J, -1>(acc, c, A);
       SYM_FAT_FENCE();
     }
-    fk2_inner<K, J + 1>(acc, c0, T1, c5, c7);
+    fk2_inner<K, J + 1>(acc, c0, w);
   }
 }
 
 template <int K, typename T>
-__device__ __forceinline__ void fk2_step(const Ctx<T>& c0, const T* T1, T* midc, const FatCoeffs& cf, int cb) {
-  if constexpr (K <= 3) {
-    su3<T> acc = c0.template u<0, 0, 0, 0, 0>();
-    const T c3 = T(cf.c[1]);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      acc.e[e].re *= c3;
-      acc.e[e].im *= c3;
-    }
-    fk2_inner<K, 1>(acc, c0, T1, T(cf.c[2]), T(cf.c[3]));
-    store_slot(midc, 3, K - 1, c0.ax[0], c0.p, c0.Vh, cb, acc);
-    fk2_step<K + 1>(c0, T1, midc, cf, cb);
-  }
-}
-
-// FK3: V_mu = c1 U_mu + sum_{K,s} Sts_{ax[K]}(midc_K + cL T1_{K,s})
-template <int K, typename T>
-__device__ __forceinline__ void fk3_step(su3<T>& acc, const Ctx<T>& c0, const T* T1, const T* midc, T cL) {
+__device__ __forceinline__ void fk2_step(const Ctx<T>& c0, const Fields<T>& w, const FatCoeffs& cf, int cb) {
   if constexpr (K <= 3) {
     Ctx<T> c = c0;
     launder(c);
-    auto Ap = comb_f<T>();
-    comb_add(Ap, midc, 3, K - 1, T(1));
-    comb_add(Ap, T1, 6, 2 * (K - 1), cL);
-    st_acc<K, 1>(acc, c, Ap);
+    su3<T> acc = c.template u<0, 0, 0, 0, 0>();
+    scale(acc, T(cf.c[1]));
+    fk2_inner<K, 1>(acc, c, w);
+    const T cL = T(cf.c[4]);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      su3<T> m = acc;
+      axpy(m, cL, c.template f<0, 0, 0, 0, 0>(w.T1, 6, 2 * (K - 1) + s));
+      store_slot(w.M, 6, 2 * (K - 1) + s, c.ax[0], c.p, c.Vh, cb, m);
+    }
     SYM_FAT_FENCE();
-    auto Am = comb_f<T>();
-    comb_add(Am, midc, 3, K - 1, T(1));
-    comb_add(Am, T1, 6, 2 * (K - 1) + 1, cL);
-    st_acc<K, -1>(acc, c, Am);
+    fk2_step<K + 1>(c0, w, cf, cb);
+  }
+}
+
+// FK3: V_mu = c1 U_mu + sum_{K,s} Sts_{ax[K]}(M[K, s])
+template <int K, typename T>
+__device__ __forceinline__ void fk3_step(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
+  if constexpr (K <= 3) {
+    Ctx<T> c = c0;
+    launder(c);
+    st_acc<K, 1>(acc, c, one(static_cast<const T*>(w.M), 6, 2 * (K - 1)));
     SYM_FAT_FENCE();
-    fk3_step<K + 1>(acc, c0, T1, midc, cL);
+    st_acc<K, -1>(acc, c, one(static_cast<const T*>(w.M), 6, 2 * (K - 1) + 1));
+    SYM_FAT_FENCE();
+    fk3_step<K + 1>(acc, c0, w);
   }
 }
 
 // ------------------------------------------------------------------ reverse
 
-// BK3: gM[mu][2(K-1) + (S<0)] = St^{-S}_{ax[K]}(GV_mu)
+// BK3: gM[K, S] = St-S_{ax[K]}(GV_mu), gmid[K-1] = gM[K, +] + gM[K, -]
 template <int K, typename T>
-__device__ __forceinline__ void bk3_step(const Ctx<T>& c0, const T* GV, T* gM, int cb) {
+__device__ __forceinline__ void bk3_step(const Ctx<T>& c0, const T* GV, const Fields<T>& w, int cb) {
   if constexpr (K <= 3) {
     Ctx<T> c = c0;
     launder(c);
-    auto G = comb_f<T>();
-    comb_add(G, GV, 1, 0, T(1));
-    su3<T> r;
+    const auto G = one(GV, 1, 0);
+    su3<T> r, gm;
     set_zero(r);
     st_acc<K, -1>(r, c, G);
-    store_slot(gM, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
+    store_slot(w.gM, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
+    gm = r;
     SYM_FAT_FENCE();
     set_zero(r);
     st_acc<K, 1>(r, c, G);
-    store_slot(gM, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
+    store_slot(w.gM, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
+    add(gm, r);
+    store_slot(w.gmid, 3, K - 1, c.ax[0], c.p, c.Vh, cb, gm);
     SYM_FAT_FENCE();
-    bk3_step<K + 1>(c0, GV, gM, cb);
+    bk3_step<K + 1>(c0, GV, w, cb);
   }
 }
 
-// BK2: g_inner[mu][M-1] = sum_{(K,J): {K,J,M} = {1,2,3}} sum_s Sts_{ax[J]}(gM_{K,+} + gM_{K,-})
+// BK2: g_inner_M = sum_{(K,J): {K,J,M} = {1,2,3}} sum_s Sts_{ax[J]}(gmid_K); stores
+// gT1[M, s] = c7 g_inner_M + cL gM[M, s]; returns c5 g_inner_M added into dsum
 template <int M, int K, typename T>
-__device__ __forceinline__ void bk2_inner(su3<T>& acc, const Ctx<T>& c0, const T* gM) {
+__device__ __forceinline__ void bk2_inner(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
   if constexpr (K <= 3) {
     if constexpr (K != M) {
       constexpr int J = 6 - K - M;
       Ctx<T> c = c0;
       launder(c);
-      auto G = comb_f<T>();
-      comb_add(G, gM, 6, 2 * (K - 1), T(1));
-      comb_add(G, gM, 6, 2 * (K - 1) + 1, T(1));
+      const auto G = one(static_cast<const T*>(w.gmid), 3, K - 1);
       st_acc<J, 1>(acc, c, G);
       SYM_FAT_FENCE();
       st_acc<J, -1>(acc, c, G);
       SYM_FAT_FENCE();
     }
-    bk2_inner<M, K + 1>(acc, c0, gM);
+    bk2_inner<M, K + 1>(acc, c0, w);
   }
 }
 
 template <int M, typename T>
-__device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const T* gM, T* ginner, int cb) {
-  if constexpr (M <= 3) {
-    su3<T> acc;
-    set_zero(acc);
-    bk2_inner<M, 1>(acc, c0, gM);
-    store_slot(ginner, 3, M - 1, c0.ax[0], c0.p, c0.Vh, cb, acc);
-    bk2_step<M + 1>(c0, gM, ginner, cb);
-  }
-}
-
-// GK, transports into U_nu (nu = ax[0]) as the transported field: St^{-S}_{ax[M]}(gT1_{M,S})
-// with gT1_{M,S} = c7 g_inner_M + cL gM_{M,S}
-template <int M, typename T>
-__device__ __forceinline__ void gk_pull(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w, T c7, T cL) {
+__device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const Fields<T>& w, const FatCoeffs& cf, su3<T>& dsum,
+                                         int cb) {
   if constexpr (M <= 3) {
     Ctx<T> c = c0;
     launder(c);
-    auto Gp = comb_f<T>();
-    comb_add(Gp, w.ginner, 3, M - 1, c7);
-    comb_add(Gp, w.gM, 6, 2 * (M - 1), cL);
-    st_acc<M, -1>(acc, c, Gp);
+    su3<T> gi;
+    set_zero(gi);
+    bk2_inner<M, 1>(gi, c, w);
+    const T c7 = T(cf.c[3]), cL = T(cf.c[4]);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      su3<T> g = c.template f<0, 0, 0, 0, 0>(w.gM, 6, 2 * (M - 1) + s);
+      scale(g, cL);
+      axpy(g, c7, gi);
+      store_slot(w.gT1, 6, 2 * (M - 1) + s, c.ax[0], c.p, c.Vh, cb, g);
+    }
+    axpy(dsum, T(cf.c[2]), gi);
     SYM_FAT_FENCE();
-    auto Gm = comb_f<T>();
-    comb_add(Gm, w.ginner, 3, M - 1, c7);
-    comb_add(Gm, w.gM, 6, 2 * (M - 1) + 1, cL);
-    st_acc<M, 1>(acc, c, Gm);
+    bk2_step<M + 1>(c0, w, cf, dsum, cb);
+  }
+}
+
+// GK, transports of U_nu's own chain: St-S_{ax[M]}(gT1[M, S])
+template <int M, typename T>
+__device__ __forceinline__ void gk_pull(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
+  if constexpr (M <= 3) {
+    Ctx<T> c = c0;
+    launder(c);
+    st_acc<M, -1>(acc, c, one(static_cast<const T*>(w.gT1), 6, 2 * (M - 1)));
     SYM_FAT_FENCE();
-    gk_pull<M + 1>(acc, c0, w, c7, cL);
+    st_acc<M, 1>(acc, c, one(static_cast<const T*>(w.gT1), 6, 2 * (M - 1) + 1));
+    SYM_FAT_FENCE();
+    gk_pull<M + 1>(acc, c0, w);
   }
 }
 
 // GK, deposits on U_{y,nu} from the transports along nu in the chains of mu = ax[I].
 template <int I, typename T>
-__device__ __forceinline__ void gk_factor(su3<T>& acc, const Ctx<T>& c0, const T* GV, const Fields<T>& w,
-                                          const FatCoeffs& cf) {
+__device__ __forceinline__ void gk_factor(su3<T>& acc, const Ctx<T>& c0, const T* GV, const Fields<T>& w) {
   if constexpr (I <= 3) {
     const int mu = c0.ax[I], nu = c0.ax[0];
     const int kn = nu < mu ? nu : nu - 1;  // index of nu among the axes other than mu
-    const T c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]);
     {
-      // V_mu = ... + Sts_nu(midc_nu + cL T1_{nu,s}) with gradient GV_mu
+      // V_mu = ... + Sts_nu(M[nu, s]) with gradient GV_mu
       Ctx<T> c = c0;
       launder(c);
-      auto G = comb_f<T>();
-      comb_add(G, GV, 1, 0, T(1));
-      auto Ap = comb_f<T>();
-      comb_add(Ap, w.midc, 3, kn, T(1));
-      comb_add(Ap, w.T1, 6, 2 * kn, cL);
-      factor_acc<I, 1>(acc, c, G, Ap);
+      const auto G = one(GV, 1, 0);
+      factor_acc<I, 1>(acc, c, G, one(static_cast<const T*>(w.M), 6, 2 * kn));
       SYM_FAT_FENCE();
-      auto Am = comb_f<T>();
-      comb_add(Am, w.midc, 3, kn, T(1));
-      comb_add(Am, w.T1, 6, 2 * kn + 1, cL);
-      factor_acc<I, -1>(acc, c, G, Am);
+      factor_acc<I, -1>(acc, c, G, one(static_cast<const T*>(w.M), 6, 2 * kn + 1));
       SYM_FAT_FENCE();
     }
     for (int k = 0; k < 3; ++k) {
       if (k == kn) continue;
-      // midc_k = ... + Sts_nu(c5 U_mu + c7 (T1_{m,+} + T1_{m,-})) with gradient gmid_k
+      // midc_k = ... + Sts_nu(inner[m]) with gradient gmid_k
       const int m = 3 - k - kn;
       Ctx<T> c = c0;
       launder(c);
-      auto G = comb_f<T>();
-      comb_add(G, w.gM, 6, 2 * k, T(1));
-      comb_add(G, w.gM, 6, 2 * k + 1, T(1));
-      auto A = comb_u<T>(c5);
-      comb_add(A, w.T1, 6, 2 * m, c7);
-      comb_add(A, w.T1, 6, 2 * m + 1, c7);
+      const auto G = one(static_cast<const T*>(w.gmid), 3, k);
+      const auto A = one(static_cast<const T*>(w.inner), 3, m);
       factor_acc<I, 1>(acc, c, G, A);
       SYM_FAT_FENCE();
       factor_acc<I, -1>(acc, c, G, A);
       SYM_FAT_FENCE();
     }
     {
-      // T1_{nu,s} = Sts_nu(U_mu) with gradient gT1_{nu,s} = c7 g_inner_nu + cL gM_{nu,s}
+      // T1[nu, s] = Sts_nu(U_mu) with gradient gT1[nu, s]
       Ctx<T> c = c0;
       launder(c);
-      const auto A = comb_u<T>(T(1));
-      auto Gp = comb_f<T>();
-      comb_add(Gp, w.ginner, 3, kn, c7);
-      comb_add(Gp, w.gM, 6, 2 * kn, cL);
-      factor_acc<I, 1>(acc, c, Gp, A);
+      const auto A = u_only<T>();
+      factor_acc<I, 1>(acc, c, one(static_cast<const T*>(w.gT1), 6, 2 * kn), A);
       SYM_FAT_FENCE();
-      auto Gm = comb_f<T>();
-      comb_add(Gm, w.ginner, 3, kn, c7);
-      comb_add(Gm, w.gM, 6, 2 * kn + 1, cL);
-      factor_acc<I, -1>(acc, c, Gm, A);
+      factor_acc<I, -1>(acc, c, one(static_cast<const T*>(w.gT1), 6, 2 * kn + 1), A);
       SYM_FAT_FENCE();
     }
-    gk_factor<I + 1>(acc, c0, GV, w, cf);
+    gk_factor<I + 1>(acc, c0, GV, w);
   }
 }
 
