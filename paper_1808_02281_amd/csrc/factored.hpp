@@ -266,12 +266,33 @@ __device__ __forceinline__ CubeB<T> load_cube_b(const FCtx<T>& c0) {
   return d;
 }
 
+// Q += l r (e > 0) or l r^dagger (e < 0) for staples l, r in SU(3) given by their first
+// two rows. The product is special unitary too, so only its first two rows are
+// multiplied out (from the two stored rows of l) and its third row is rebuilt from
+// them: 18 complex multiply-adds and one rebuild instead of 27 and two.
 template <int J, typename T>
-__device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Rows2<T>& r) {
-  if constexpr (e_sign(J) > 0)
-    mac<false, false>(Q, full(l), full(r));
-  else
-    mac<false, true>(Q, full(l), full(r));
+__device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Rows2<T>& r2) {
+  const su3<T> r = full(r2);
+  su3<T> P;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T re = T(0), im = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const cx<T> x = l.e[3 * i + k];
+        const cx<T> y = elem<(e_sign(J) < 0)>(r, k, j);
+        re = fma(x.re, y.re, re);
+        im = fma(x.re, y.im, im);
+        re = fma(-x.im, y.im, re);
+        im = fma(x.im, y.re, im);
+      }
+      P.e[3 * i + j] = cx<T>{re, im};
+    }
+  }
+  complete_third_row(P);
+  add(Q, P);
 }
 
 template <int J, typename T>
