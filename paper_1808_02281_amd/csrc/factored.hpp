@@ -266,14 +266,12 @@ __device__ __forceinline__ CubeB<T> load_cube_b(const FCtx<T>& c0) {
   return d;
 }
 
-// Q += l r (e > 0) or l r^dagger (e < 0) for staples l, r in SU(3) given by their first
-// two rows. The product is special unitary too, so only its first two rows are
-// multiplied out (from the two stored rows of l) and its third row is rebuilt from
-// them: 18 complex multiply-adds and one rebuild instead of 27 and two.
-template <int J, typename T>
-__device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Rows2<T>& r2) {
-  const su3<T> r = full(r2);
-  su3<T> P;
+// The first two rows of l r^{DB} for l given by its two stored rows and r in full; the
+// product of two special-unitary matrices is special unitary, so full() of the result
+// rebuilds its third row.
+template <bool DB, typename T>
+__device__ __forceinline__ Rows2<T> rows_mul(const Rows2<T>& l, const su3<T>& r) {
+  Rows2<T> P;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
 #pragma unroll
@@ -282,7 +280,7 @@ __device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Row
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const cx<T> x = l.e[3 * i + k];
-        const cx<T> y = elem<(e_sign(J) < 0)>(r, k, j);
+        const cx<T> y = elem<DB>(r, k, j);
         re = fma(x.re, y.re, re);
         im = fma(x.re, y.im, im);
         re = fma(-x.im, y.im, re);
@@ -291,19 +289,23 @@ __device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Row
       P.e[3 * i + j] = cx<T>{re, im};
     }
   }
-  complete_third_row(P);
-  add(Q, P);
+  return P;
+}
+
+// Q += l r (e > 0) or l r^dagger (e < 0) for staples l, r in SU(3) given by their first
+// two rows. The product is special unitary too, so only its first two rows are
+// multiplied out (from the two stored rows of l) and its third row is rebuilt from
+// them: 18 complex multiply-adds and one rebuild instead of 27 and two.
+template <int J, typename T>
+__device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Rows2<T>& r) {
+  add(Q, full(rows_mul<(e_sign(J) < 0)>(l, full(r))));
 }
 
 template <int J, typename T>
 __device__ __forceinline__ void use_cube_b(su3<T>& t, su3<T>& Q, const CubeB<T>& d, T cR, T cC) {
   cube_mac<J>(Q, d.l2, d.r2);
   cube_mac<J>(Q, d.l3, d.r3);
-  su3<T> R;
-  if constexpr (e_sign(J) > 0)
-    R = mul<false, true>(full(d.see), d.lnk);
-  else
-    R = mul<false, false>(full(d.see), d.lnk);
+  su3<T> R = full(rows_mul<(e_sign(J) > 0)>(d.see, d.lnk));  // S(x+e,mu,e) U_{x,e}^dag (special unitary)
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     R.e[i].re = fma(cC, Q.e[i].re, cR * R.e[i].re);
@@ -413,14 +415,14 @@ __device__ __forceinline__ void long_pipe(const FCtx<T>& c, su3<T>& tP, su3<T>& 
     SYM_FENCE();
     const su3<T> sx = full(d.sx);
     add(tP, sx);
-    mac<false, false>(RA, full(d.sp), sx);
+    add(RA, full(rows_mul<false>(d.sp, sx)));
     mac<false, false>(RB, sx, full(d.sm));
     SYM_FENCE();
     long_pipe<J + 1>(c, tP, RA, RB, dn);
   } else {
     const su3<T> sx = full(d.sx);
     add(tP, sx);
-    mac<false, false>(RA, full(d.sp), sx);
+    add(RA, full(rows_mul<false>(d.sp, sx)));
     mac<false, false>(RB, sx, full(d.sm));
   }
 }
