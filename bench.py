@@ -323,6 +323,40 @@ def bench_wilson(sym, torch, U_np, L, steps, warmup, with_fp64=True, with_cpu=Tr
     return out
 
 
+def bench_autograd(sym, torch, gaugegen, u0, beta, steps, warmup):
+    """Differentiation on the 24^3x48 workload (links eps 0.3, seed 3): S_G through
+    torch autograd, forward = action kernel, backward = force kernels (2 G U per link);
+    one step = forward + backward."""
+    cfg = gaugegen.CONFIGS["thermal_24x24x24x48"]
+    L = cfg["L"]
+    dev = torch.device("cuda:0")
+    links = 4 * sym.volume(L)
+    aos = gaugegen.near_thermal_links_device(L, cfg["eps"], cfg["seed"], dev)
+    out = {"workload": "thermal_24x24x24x48", "links": links}
+    for prec, cdt in (("f32", torch.complex64), ("f64", torch.complex128)):
+        U = sym.pack(aos.to(cdt), L).requires_grad_(True)
+
+        def step():
+            U.grad = None
+            S = sym.symanzik_action(U, L, u0, beta)
+            S.backward()
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[prec] = {"ms_per_forward_backward": ms, "link_gradients_per_s": links / (ms * 1e-3)}
+        log(f"  autograd {prec}: {ms:.3f} ms per forward + backward")
+        del U
+    return out
+
+
 def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
     """The FP64 oracle's force on a random sample of links of the same workload."""
     import numpy as np
@@ -372,6 +406,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fat", action="store_true", help="skip the fat-link path force")
     ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-clover force")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd timing")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -393,7 +428,7 @@ def main():
 
     if args.only_f32:
         args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = args.no_fat = True
-        args.no_wilson = True
+        args.no_wilson = args.no_autograd = True
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]
@@ -499,6 +534,10 @@ def main():
         out["md_leapfrog"] = {"prec": "f32", "nsteps": nst, "dt": 0.02, "ms_per_step": ms / nst,
                               "link_updates_per_s": links * nst / (ms * 1e-3)}
         del P, Um
+
+    if not args.no_autograd:
+        log("timing autograd (24^3x48)")
+        out["autograd"] = bench_autograd(sym, torch, gaugegen, u0, beta, args.steps, args.warmup)
 
     if not args.no_batch:
         log("timing the 64-lattice batch")

@@ -193,3 +193,26 @@ def test_two_level_chain_finite_differences(sym):
             fd = (phi(Us + eps * E) - phi(Us - eps * E)).item() / (2 * eps)
         an = (grad * E).sum().item()
         assert abs(fd - an) <= 1e-7 * abs(an), (fd, an)
+
+
+def test_graph_replay_matches_eager(sym):
+    """The path force is plain kernel launches on the caller's stream: captured once into
+    a HIP graph, every replay (with eager work in between) reproduces the eager result."""
+    L = (6, 6, 6, 8)
+    U, GV, GW = _inputs(L, 30, "f32")
+    dev = device()
+    Us, GVs, GWs = (to_soa(sym, X, L, "f32", dev) for X in (U, GV, GW))
+    eager = sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, mode="force")
+    out = torch.empty_like(Us)
+    sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, mode="force", out=out)  # warm the workspace cache
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, mode="force", out=out)
+    for rep in range(3):
+        out.zero_()
+        sym.fat_links(Us, L, C_GENERIC)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep}"

@@ -91,3 +91,26 @@ def test_wilson_force_32x32x32x64_sampled(sym, prec):
     e = force_errors(Gs, Go)
     print(f"  32^3x64 {prec}: max {e[0]:.2e} rms {e[1]:.2e}")
     assert e[0] <= TOL[prec]
+
+
+def test_graph_replay_matches_eager(sym):
+    L = (6, 6, 6, 8)
+    U = rounded(gaugegen.near_thermal_links(L, 0.35, 47), "f32")
+    X, Y = _spinor_np(L, 48, "f32"), _spinor_np(L, 49, "f32")
+    dev = device()
+    Us = to_soa(sym, U, L, "f32", dev)
+    Xs, Ys = _to_dev_spinor(sym, X, L, "f32"), _to_dev_spinor(sym, Y, L, "f32")
+    eager = sym.wilson_force(Us, Xs, Ys, L, KAPPA, CSW)
+    out = torch.empty_like(Us)
+    sym.wilson_force(Us, Xs, Ys, L, KAPPA, CSW, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sym.wilson_force(Us, Xs, Ys, L, KAPPA, CSW, out=out)
+    for rep in range(3):
+        out.zero_()
+        sym.wilson_force(Us, Ys, Xs, L, KAPPA, 0.0)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep}"
