@@ -115,7 +115,10 @@ __global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restr
     SYM_FAT_FENCE();
   }
 
-  fat::gk_factor<1>(acc, c, GV, w);
+  if constexpr (sizeof(T) == 4)
+    fat::gk_factor_pipe<1>(acc, c, GV, w);
+  else
+    fat::gk_factor<1>(acc, c, GV, w);
 
   fat::launder(c);
   cx<T>* dst = block_ptr(out, lt.mu, lt.p, g.Vh);

@@ -492,6 +492,114 @@ __device__ __forceinline__ void gk_factor(su3<T>& acc, const Ctx<T>& c0, const T
   }
 }
 
+// GK deposits, software-pipelined (FP32). For mu = ax[I] the eight transports along nu
+// deposit acc += X0 U_{y+mu,nu} Y0^dag + X1^dag U_{y-mu,nu} Y1 with, for sign +,
+// (X0, X1, Y0, Y1) = (G_y, G_{y-mu}, A_{y+nu}, A_{y-mu+nu}) and, for sign -,
+// (A_y, A_{y-mu}, G_{y+nu}, G_{y-mu+nu}) (see factor_acc). The two links are loaded once
+// per mu, and the four matrices of the next transport are requested before the
+// current one is multiplied out.
+template <typename T>
+struct Dep {
+  su3<T> x0, x1, y0, y1;
+};
+
+template <int I, int K, typename T>
+__device__ __forceinline__ Dep<T> load_dep(const Ctx<T>& c0, const T* GV, const Fields<T>& w, int kn) {
+  constexpr int e1 = comp(1, I), e2 = comp(2, I), e3 = comp(3, I);
+  constexpr bool plus = (K % 2) == 0;
+  Ctx<T> c = c0;
+  launder(c);
+  // fields of the K-th transport: K = 0,1: (GV, M[nu,s]); 2..5: (gmid[k], inner[m]);
+  // 6,7: (gT1[nu,s], U_mu)
+  const T* gf;
+  int gn, gs;
+  const T* af = nullptr;
+  int an = 1, as = 0;
+  if constexpr (K < 2) {
+    gf = GV;
+    gn = 1;
+    gs = 0;
+    af = w.M;
+    an = 6;
+    as = 2 * kn + (K & 1);
+  } else if constexpr (K < 6) {
+    const int j = (K - 2) / 2;  // j-th of the two axes other than mu and nu
+    const int k = (j == 0) ? (kn == 0 ? 1 : 0) : (kn == 2 ? 1 : 2);
+    gf = w.gmid;
+    gn = 3;
+    gs = k;
+    af = w.inner;
+    an = 3;
+    as = 3 - k - kn;
+  } else {
+    gf = w.gT1;
+    gn = 6;
+    gs = 2 * kn + (K & 1);
+  }
+  asm volatile("" : "+s"(gf), "+s"(af));
+  Dep<T> d;
+  if constexpr (plus) {
+    d.x0 = c.template f<0, 0, 0, 0, I>(gf, gn, gs);
+    d.x1 = c.template f<0, -e1, -e2, -e3, I>(gf, gn, gs);
+    if constexpr (K < 6) {
+      d.y0 = c.template f<1, 0, 0, 0, I>(af, an, as);
+      d.y1 = c.template f<1, -e1, -e2, -e3, I>(af, an, as);
+    } else {
+      d.y0 = c.template u<1, 0, 0, 0, I>();
+      d.y1 = c.template u<1, -e1, -e2, -e3, I>();
+    }
+  } else {
+    if constexpr (K < 6) {
+      d.x0 = c.template f<0, 0, 0, 0, I>(af, an, as);
+      d.x1 = c.template f<0, -e1, -e2, -e3, I>(af, an, as);
+    } else {
+      d.x0 = c.template u<0, 0, 0, 0, I>();
+      d.x1 = c.template u<0, -e1, -e2, -e3, I>();
+    }
+    d.y0 = c.template f<1, 0, 0, 0, I>(gf, gn, gs);
+    d.y1 = c.template f<1, -e1, -e2, -e3, I>(gf, gn, gs);
+  }
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ void use_dep(su3<T>& acc, const Dep<T>& d, const su3<T>& up, const su3<T>& um) {
+  mac<false, true>(acc, mul<false, false>(d.x0, up), d.y0);
+  mac<false, false>(acc, mul<true, false>(d.x1, um), d.y1);
+}
+
+template <int I, int K, typename T>
+__device__ __forceinline__ void dep_pipe(su3<T>& acc, const Ctx<T>& c, const T* GV, const Fields<T>& w, int kn,
+                                         const su3<T>& up, const su3<T>& um, const Dep<T>& d) {
+  if constexpr (K < 7) {
+    const Dep<T> dn = load_dep<I, K + 1>(c, GV, w, kn);
+    SYM_FAT_FENCE();
+    use_dep(acc, d, up, um);
+    SYM_FAT_FENCE();
+    dep_pipe<I, K + 1>(acc, c, GV, w, kn, up, um, dn);
+  } else {
+    use_dep(acc, d, up, um);
+    SYM_FAT_FENCE();
+  }
+}
+
+template <int I, typename T>
+__device__ __forceinline__ void gk_factor_pipe(su3<T>& acc, const Ctx<T>& c0, const T* GV, const Fields<T>& w) {
+  if constexpr (I <= 3) {
+    constexpr int e1 = comp(1, I), e2 = comp(2, I), e3 = comp(3, I);
+    const int mu = c0.ax[I], nu = c0.ax[0];
+    const int kn = nu < mu ? nu : nu - 1;
+    Ctx<T> c = c0;
+    launder(c);
+    const su3<T> up = c.template u<0, e1, e2, e3, 0>();     // U_{y+mu,nu}
+    const su3<T> um = c.template u<0, -e1, -e2, -e3, 0>();  // U_{y-mu,nu}
+    const Dep<T> d0 = load_dep<I, 0>(c, GV, w, kn);
+    SYM_FAT_FENCE();
+    dep_pipe<I, 0>(acc, c, GV, w, kn, up, um, d0);
+    gk_factor_pipe<I + 1>(acc, c0, GV, w);
+  }
+}
+
 }  // namespace fat
 }  // namespace sym
 
