@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void fat_gk_kernel(Geom g, const T* __restr
   if constexpr (sizeof(T) == 4)
     fat::gk_factor_pipe<1>(acc, c, GV, w);
   else
-    fat::gk_factor<1>(acc, c, GV, w);
+    fat::gk_factor_links_once<1>(acc, c, GV, w);
 
   fat::launder(c);
   cx<T>* dst = block_ptr(out, lt.mu, lt.p, g.Vh);
