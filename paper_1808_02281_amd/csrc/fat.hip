@@ -29,7 +29,28 @@ __global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __rest
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  fat::fk2_step<1>(c, w, cf, cb);
+  if constexpr (sizeof(T) == 4) {
+    su3<T> acc[3];
+    const su3<T> u = c.template u<0, 0, 0, 0, 0>();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc[k] = u;
+      fat::scale(acc[k], T(cf.c[1]));
+    }
+    SYM_FAT_FENCE();
+    fat::two_out<1, false>(acc, c, static_cast<const T*>(w.inner));
+    fat::launder(c);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        su3<T> m = acc[k];
+        axpy(m, T(cf.c[4]), c.template f<0, 0, 0, 0, 0>(w.T1, 6, 2 * k + s));
+        fat::store_slot(w.M, 6, 2 * k + s, lt.mu, lt.p, g.Vh, cb, m);
+      }
+  } else {
+    fat::fk2_step<1>(c, w, cf, cb);
+  }
 }
 
 template <typename T>
@@ -78,7 +99,27 @@ __global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __rest
   fat::scale(dsum, T(cf.c[0]));
   for (int k = 0; k < 3; ++k) axpy(dsum, T(cf.c[1]), c.template f<0, 0, 0, 0, 0>(w.gmid, 3, k));
   SYM_FAT_FENCE();
-  fat::bk2_step<1>(c, w, cf, dsum, cb);
+  if constexpr (sizeof(T) == 4) {
+    su3<T> gi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) set_zero(gi[k]);
+    fat::two_out<1, true>(gi, c, static_cast<const T*>(w.gmid));
+    fat::launder(c);
+    const T c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        su3<T> gt = c.template f<0, 0, 0, 0, 0>(w.gM, 6, 2 * m + s);
+        fat::scale(gt, cL);
+        axpy(gt, c7, gi[m]);
+        fat::store_slot(w.gT1, 6, 2 * m + s, lt.mu, lt.p, g.Vh, cb, gt);
+      }
+      axpy(dsum, c5, gi[m]);
+    }
+  } else {
+    fat::bk2_step<1>(c, w, cf, dsum, cb);
+  }
   fat::store_slot(w.D, 1, 0, lt.mu, lt.p, g.Vh, cb, dsum);
 }
 

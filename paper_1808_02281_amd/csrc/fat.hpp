@@ -413,6 +413,48 @@ __device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const Fields<T>& w, c
   }
 }
 
+// FK2 and BK2 with the transport direction J outermost (FP32): each transport along
+// ax[J] serves two outputs, so its four links (U_{x,J}, U_{x+mu,J}, U_{x-J,J},
+// U_{x-J+mu,J}) are loaded once for both; the three accumulators stay in registers.
+// acc[K-1] += sum_s Sts_{ax[J]}(F[slot(K)]) for the two K != J, where (K, J, M) is a
+// permutation of (1, 2, 3) and the transported field is inner[M-1] (FK2: outputs
+// midc_K) or gmid[K-1] into output g_inner_M (BK2, with the roles of K and M swapped).
+template <int J, int K, bool BACK, typename T>
+__device__ __forceinline__ void two_out_step(su3<T> (&acc)[3], const Ctx<T>& c, const T* F, const su3<T>& u0,
+                                             const su3<T>& u1, const su3<T>& v0, const su3<T>& v1) {
+  if constexpr (K <= 3) {
+    if constexpr (K != J) {
+      constexpr int M = 6 - K - J;
+      constexpr int e1 = comp(1, J), e2 = comp(2, J), e3 = comp(3, J);
+      // FK2: output midc_K from inner_M; BK2: output g_inner_M from gmid_K
+      constexpr int out = BACK ? M - 1 : K - 1;
+      constexpr int src = BACK ? K - 1 : M - 1;
+      const su3<T> ap = c.template f<0, e1, e2, e3, 0>(F, 3, src);
+      mac<false, true>(acc[out], mul<false, false>(u0, ap), u1);
+      const su3<T> am = c.template f<0, -e1, -e2, -e3, 0>(F, 3, src);
+      mac<false, false>(acc[out], mul<true, false>(v0, am), v1);
+      SYM_FAT_FENCE();
+    }
+    two_out_step<J, K + 1, BACK>(acc, c, F, u0, u1, v0, v1);
+  }
+}
+
+template <int J, bool BACK, typename T>
+__device__ __forceinline__ void two_out(su3<T> (&acc)[3], const Ctx<T>& c0, const T* F) {
+  if constexpr (J <= 3) {
+    constexpr int e1 = comp(1, J), e2 = comp(2, J), e3 = comp(3, J);
+    Ctx<T> c = c0;
+    launder(c);
+    asm volatile("" : "+s"(F));
+    const su3<T> u0 = c.template u<0, 0, 0, 0, J>();              // U_{x,J}
+    const su3<T> u1 = c.template u<1, 0, 0, 0, J>();              // U_{x+mu,J}
+    const su3<T> v0 = c.template u<0, -e1, -e2, -e3, J>();        // U_{x-J,J}
+    const su3<T> v1 = c.template u<1, -e1, -e2, -e3, J>();        // U_{x-J+mu,J}
+    two_out_step<J, 1, BACK>(acc, c, F, u0, u1, v0, v1);
+    two_out<J + 1, BACK>(acc, c0, F);
+  }
+}
+
 // GK, transports of U_nu's own chain: St-S_{ax[M]}(gT1[M, S])
 template <int M, typename T>
 __device__ __forceinline__ void gk_pull(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
