@@ -38,10 +38,10 @@ BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 # Fat-link path force (asqtad/HISQ smearing), flop per link of each kernel, counted from
 # the kernel source: SU(3) product 198, product accumulated into a matrix 216, matrix
 # axpy 36, matrix scaling or addition 18 (see the design notes for the breakdown).
-FAT_FLOP = {"fat_fk1": 2754, "fat_fk2": 5238, "fat_fk3": 2916, "fat_bk3": 2538, "fat_bk2": 5526,
+FAT_FLOP = {"fat_fk1": 2754, "fat_fk2": 7722, "fat_fk3": 2916, "fat_bk3": 2538, "fat_bk2": 8010,
             "fat_gk": 23418}
 # minimum HBM matrices (18 reals) read + written per link by each kernel
-FAT_MATRICES = {"fat_fk1": 10, "fat_fk2": 16, "fat_fk3": 9, "fat_bk3": 11, "fat_bk2": 18, "fat_gk": 22}
+FAT_MATRICES = {"fat_fk1": 4, "fat_fk2": 10, "fat_fk3": 9, "fat_bk3": 5, "fat_bk2": 12, "fat_gk": 22}
 C_ASQTAD = (5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
 
 # Wilson-clover force, flop per link (force kernel: 6 clover plaquettes of 9 products

@@ -172,7 +172,7 @@ int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec
  *                       with dPhi/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U:
  *                       the same convention as the gauge force G of sym_force, so the
  *                       two add.
- * ws: at least sym_fat_workspace_bytes(L, prec) bytes (31 matrices per link of
+ * ws: at least sym_fat_workspace_bytes(L, prec) bytes (19 matrices per link of
  * intermediate fields). Errors and asynchrony as for sym_force.
  */
 typedef enum { SYM_FAT_GRAD = 0, SYM_FAT_FORCE = 1 } sym_fat_mode;

@@ -343,13 +343,11 @@ sym::fat::Fields<T> fat_carve(void* ws, const Geom& g, int prec) {
   const size_t one = align256(link_field_bytes(g, prec));
   char* p = static_cast<char*>(ws);
   sym::fat::Fields<T> w;
-  w.T1 = reinterpret_cast<T*>(p);
-  w.inner = reinterpret_cast<T*>(p + 6 * one);
-  w.M = reinterpret_cast<T*>(p + 9 * one);
-  w.gM = reinterpret_cast<T*>(p + 15 * one);
-  w.gmid = reinterpret_cast<T*>(p + 21 * one);
-  w.gT1 = reinterpret_cast<T*>(p + 24 * one);
-  w.D = reinterpret_cast<T*>(p + 30 * one);
+  w.inner = reinterpret_cast<T*>(p);
+  w.M = reinterpret_cast<T*>(p + 3 * one);
+  w.gmid = reinterpret_cast<T*>(p + 9 * one);
+  w.gT1 = reinterpret_cast<T*>(p + 12 * one);
+  w.D = reinterpret_cast<T*>(p + 18 * one);
   return w;
 }
 

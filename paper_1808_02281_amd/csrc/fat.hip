@@ -40,14 +40,12 @@ __global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __rest
     SYM_FAT_FENCE();
     fat::two_out<1, false>(acc, c, static_cast<const T*>(w.inner));
     fat::launder(c);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        su3<T> m = acc[k];
-        axpy(m, T(cf.c[4]), c.template f<0, 0, 0, 0, 0>(w.T1, 6, 2 * k + s));
-        fat::store_slot(w.M, 6, 2 * k + s, lt.mu, lt.p, g.Vh, cb, m);
-      }
+    SYM_FAT_FENCE();
+    fat::store_m<1>(acc[0], c, w, T(cf.c[4]), cb);
+    SYM_FAT_FENCE();
+    fat::store_m<2>(acc[1], c, w, T(cf.c[4]), cb);
+    SYM_FAT_FENCE();
+    fat::store_m<3>(acc[2], c, w, T(cf.c[4]), cb);
   } else {
     fat::fk2_step<1>(c, w, cf, cb);
   }
@@ -106,19 +104,16 @@ __global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __rest
     fat::two_out<1, true>(gi, c, static_cast<const T*>(w.gmid));
     fat::launder(c);
     const T c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]);
+    SYM_FAT_FENCE();
+    fat::store_gt<1>(gi[0], c, GV, w, c7, cL, cb);
+    SYM_FAT_FENCE();
+    fat::store_gt<2>(gi[1], c, GV, w, c7, cL, cb);
+    SYM_FAT_FENCE();
+    fat::store_gt<3>(gi[2], c, GV, w, c7, cL, cb);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        su3<T> gt = c.template f<0, 0, 0, 0, 0>(w.gM, 6, 2 * m + s);
-        fat::scale(gt, cL);
-        axpy(gt, c7, gi[m]);
-        fat::store_slot(w.gT1, 6, 2 * m + s, lt.mu, lt.p, g.Vh, cb, gt);
-      }
-      axpy(dsum, c5, gi[m]);
-    }
+    for (int m = 0; m < 3; ++m) axpy(dsum, c5, gi[m]);
   } else {
-    fat::bk2_step<1>(c, w, cf, dsum, cb);
+    fat::bk2_step<1>(c, GV, w, cf, dsum, cb);
   }
   fat::store_slot(w.D, 1, 0, lt.mu, lt.p, g.Vh, cb, dsum);
 }

@@ -226,26 +226,25 @@ __device__ __forceinline__ UOnly<T> u_only() {
   return o;
 }
 
-// Workspace fields of one lattice (slot fields X[mu][p][slot][9][V/2]):
-//   T1[2k + (s<0)] = Sts_{a_k}(U_mu)                       (6 slots, pass FK1)
+// Workspace fields of one lattice (slot fields X[mu][p][slot][9][V/2]), with
+// T1[2k + (s<0)] = Sts_{a_k}(U_mu) and gM[2k + (s<0)] = St-s_{a_k}(GV_mu) (a_k the k-th
+// axis other than mu, ascending), which are not stored: the passes that need them at
+// their own site multiply them out again (two products each).
 //   inner[m] = c5 U_mu + c7 (T1[2m] + T1[2m+1])             (3 slots, FK1)
 //   M[2k + (s<0)] = midc_k + cL T1[2k + (s<0)]              (6 slots, FK2)
-//   gM[2k + (s<0)] = St-s_{a_k}(GV_mu)                      (6 slots, BK3)
 //   gmid[k] = gM[2k] + gM[2k+1]                             (3 slots, BK3)
 //   gT1[2m + (s<0)] = c7 g_inner_m + cL gM[2m + (s<0)]      (6 slots, BK2)
 //   D = c1 GV + c3 sum_k gmid_k + c5 sum_m g_inner_m        (1 slot,  BK2)
-// with a_k the k-th axis other than mu (ascending). 31 matrices per link.
+// 19 matrices per link.
 template <typename T>
 struct Fields {
-  T* T1;
   T* inner;
   T* M;
-  T* gM;
   T* gmid;
   T* gT1;
   T* D;
 };
-constexpr int kFatFields = 31;
+constexpr int kFatFields = 19;
 
 struct FatCoeffs {
   double c[6];  // c1, c3, c5, c7, cL, cN
@@ -268,7 +267,7 @@ __device__ __forceinline__ void scale(su3<T>& a, T s) {
 
 // ------------------------------------------------------------------ forward
 
-// FK1: T1 = Sts_{ax[K]}(U_mu) and inner[K-1] = c5 U + c7 (T1_{K,+} + T1_{K,-})
+// FK1: inner[K-1] = c5 U + c7 (T1_{K,+} + T1_{K,-}) with T1_{K,s} = Sts_{ax[K]}(U_mu)
 template <int K, typename T>
 __device__ __forceinline__ void fk1_step(const Ctx<T>& c0, const Fields<T>& w, T c5, T c7, int cb) {
   if constexpr (K <= 3) {
@@ -278,19 +277,60 @@ __device__ __forceinline__ void fk1_step(const Ctx<T>& c0, const Fields<T>& w, T
     su3<T> r;
     set_zero(r);
     st_acc<K, 1>(r, c, A);
-    store_slot(w.T1, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
     su3<T> in = c.template u<0, 0, 0, 0, 0>();
     scale(in, c5);
     axpy(in, c7, r);
     SYM_FAT_FENCE();
     set_zero(r);
     st_acc<K, -1>(r, c, A);
-    store_slot(w.T1, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
     axpy(in, c7, r);
     store_slot(w.inner, 3, K - 1, c.ax[0], c.p, c.Vh, cb, in);
     SYM_FAT_FENCE();
     fk1_step<K + 1>(c0, w, c5, c7, cb);
   }
+}
+
+// M[K, s] = midc_K + cL T1_{K,s}, with T1_{K,s} = Sts_{ax[K]}(U_mu) multiplied out again
+// here (two products) rather than stored by FK1 and read back
+template <int K, typename T>
+__device__ __forceinline__ void store_m(const su3<T>& midc, const Ctx<T>& c0, const Fields<T>& w, T cL, int cb) {
+  Ctx<T> c = c0;
+  launder(c);
+  const auto A = u_only<T>();
+  su3<T> t;
+  set_zero(t);
+  st_acc<K, 1>(t, c, A);
+  su3<T> m = midc;
+  axpy(m, cL, t);
+  store_slot(w.M, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, m);
+  SYM_FAT_FENCE();
+  set_zero(t);
+  st_acc<K, -1>(t, c, A);
+  m = midc;
+  axpy(m, cL, t);
+  store_slot(w.M, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, m);
+}
+
+// gT1[M, s] = c7 g_inner_M + cL gM[M, s], with gM[M, s] = St-s_{ax[M]}(GV_mu) multiplied
+// out again here rather than stored by BK3 and read back
+template <int M, typename T>
+__device__ __forceinline__ void store_gt(const su3<T>& gi, const Ctx<T>& c0, const T* GV, const Fields<T>& w, T c7,
+                                         T cL, int cb) {
+  Ctx<T> c = c0;
+  launder(c);
+  const auto G = one(GV, 1, 0);
+  su3<T> t;
+  set_zero(t);
+  st_acc<M, -1>(t, c, G);
+  scale(t, cL);
+  axpy(t, c7, gi);
+  store_slot(w.gT1, 6, 2 * (M - 1), c.ax[0], c.p, c.Vh, cb, t);
+  SYM_FAT_FENCE();
+  set_zero(t);
+  st_acc<M, 1>(t, c, G);
+  scale(t, cL);
+  axpy(t, c7, gi);
+  store_slot(w.gT1, 6, 2 * (M - 1) + 1, c.ax[0], c.p, c.Vh, cb, t);
 }
 
 // FK2: midc_K = c3 U_mu + sum_{J != K} sum_s Sts_{ax[J]}(inner[M]), M the third axis;
@@ -321,12 +361,8 @@ __device__ __forceinline__ void fk2_step(const Ctx<T>& c0, const Fields<T>& w, c
     scale(acc, T(cf.c[1]));
     fk2_inner<K, 1>(acc, c, w);
     const T cL = T(cf.c[4]);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      su3<T> m = acc;
-      axpy(m, cL, c.template f<0, 0, 0, 0, 0>(w.T1, 6, 2 * (K - 1) + s));
-      store_slot(w.M, 6, 2 * (K - 1) + s, c.ax[0], c.p, c.Vh, cb, m);
-    }
+    SYM_FAT_FENCE();
+    store_m<K>(acc, c, w, cL, cb);
     SYM_FAT_FENCE();
     fk2_step<K + 1>(c0, w, cf, cb);
   }
@@ -348,7 +384,7 @@ __device__ __forceinline__ void fk3_step(su3<T>& acc, const Ctx<T>& c0, const Fi
 
 // ------------------------------------------------------------------ reverse
 
-// BK3: gM[K, S] = St-S_{ax[K]}(GV_mu), gmid[K-1] = gM[K, +] + gM[K, -]
+// BK3: gmid[K-1] = gM[K, +] + gM[K, -] with gM[K, S] = St-S_{ax[K]}(GV_mu)
 template <int K, typename T>
 __device__ __forceinline__ void bk3_step(const Ctx<T>& c0, const T* GV, const Fields<T>& w, int cb) {
   if constexpr (K <= 3) {
@@ -358,12 +394,10 @@ __device__ __forceinline__ void bk3_step(const Ctx<T>& c0, const T* GV, const Fi
     su3<T> r, gm;
     set_zero(r);
     st_acc<K, -1>(r, c, G);
-    store_slot(w.gM, 6, 2 * (K - 1), c.ax[0], c.p, c.Vh, cb, r);
     gm = r;
     SYM_FAT_FENCE();
     set_zero(r);
     st_acc<K, 1>(r, c, G);
-    store_slot(w.gM, 6, 2 * (K - 1) + 1, c.ax[0], c.p, c.Vh, cb, r);
     add(gm, r);
     store_slot(w.gmid, 3, K - 1, c.ax[0], c.p, c.Vh, cb, gm);
     SYM_FAT_FENCE();
@@ -391,25 +425,19 @@ __device__ __forceinline__ void bk2_inner(su3<T>& acc, const Ctx<T>& c0, const F
 }
 
 template <int M, typename T>
-__device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const Fields<T>& w, const FatCoeffs& cf, su3<T>& dsum,
-                                         int cb) {
+__device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const T* GV, const Fields<T>& w, const FatCoeffs& cf,
+                                         su3<T>& dsum, int cb) {
   if constexpr (M <= 3) {
     Ctx<T> c = c0;
     launder(c);
     su3<T> gi;
     set_zero(gi);
     bk2_inner<M, 1>(gi, c, w);
-    const T c7 = T(cf.c[3]), cL = T(cf.c[4]);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      su3<T> g = c.template f<0, 0, 0, 0, 0>(w.gM, 6, 2 * (M - 1) + s);
-      scale(g, cL);
-      axpy(g, c7, gi);
-      store_slot(w.gT1, 6, 2 * (M - 1) + s, c.ax[0], c.p, c.Vh, cb, g);
-    }
+    SYM_FAT_FENCE();
+    store_gt<M>(gi, c, GV, w, T(cf.c[3]), T(cf.c[4]), cb);
     axpy(dsum, T(cf.c[2]), gi);
     SYM_FAT_FENCE();
-    bk2_step<M + 1>(c0, w, cf, dsum, cb);
+    bk2_step<M + 1>(c0, GV, w, cf, dsum, cb);
   }
 }
 

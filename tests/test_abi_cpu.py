@@ -126,10 +126,10 @@ def test_layout_and_switch_validation(L_):
 def test_fat_validation(L_):
     ok = _dims(4, 4, 4, 4)
     c = (ctypes.c_double * 6)(5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
-    # 31 link fields of intermediates
+    # 19 link fields of intermediates
     n32 = L_.sym_fat_workspace_bytes(ok, 1)
-    assert n32 >= 31 * 4 * 256 * 9 * 8
-    assert L_.sym_fat_workspace_bytes(ok, 2) >= 2 * 31 * 4 * 256 * 9 * 8
+    assert n32 >= 19 * 4 * 256 * 9 * 8
+    assert L_.sym_fat_workspace_bytes(ok, 2) >= 2 * 19 * 4 * 256 * 9 * 8
     assert L_.sym_fat_workspace_bytes(_dims(4, 4, 4, 3), 1) == 0
     fl = L_.sym_fat_links
     assert fl(ok, 1, None, FAKE, FAKE, None, FAKE, HUGE, None) == -2
