@@ -47,9 +47,10 @@ C_ASQTAD = (5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
 # Wilson-clover force, flop per link (force kernel: 6 clover plaquettes of 9 products
 # each with the insertions, hopping outer products, U B' and C' U^+, TA) and per link of
 # the clover-insertion pass (6 colour matrices per site from X, Y); minimum bytes per
-# link in reals: force = U + G + a quarter of the site's X, Y (24 complex) and K (54 complex).
+# link in reals: force = U (two rows) + G + a quarter of the site's X, Y (24 complex) and
+# K (six anti-Hermitian matrices, 9 reals each).
 WILSON_FLOP = {"wilson_force": 12450, "wilson_clover": 500}
-WILSON_REALS = {"wilson_force": 18 + 18 + (48 + 108) / 4, "wilson_clover": (48 + 108) / 4}
+WILSON_REALS = {"wilson_force": 12 + 18 + (48 + 54) / 4, "wilson_clover": (48 + 54) / 4}
 KAPPA, CSW = 0.1242, 1.37
 
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts packed FMA)

@@ -195,8 +195,10 @@ int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U
  * derivative of eq. 18_6_24_0; X = (D^+ D)^{-1} phi and Y = D X in an HMC, any fixed
  * vectors here). G is traceless antihermitian in the convention of sym_force; the
  * pseudofermion action at fixed X, Y changes by -dPsi, so its force is -G.
- * kappa, c_sw: finite. U: link field; X, Y: spinor fields (read); G: link layout (out).
- * ws: at least sym_wilson_workspace_bytes(L, prec) bytes (6 colour matrices per site).
+ * kappa, c_sw: finite. U: link field, special unitary to working precision (links are
+ * read as two rows and the third rebuilt); X, Y: spinor fields (read); G: link layout
+ * (out). ws: at least sym_wilson_workspace_bytes(L, prec) bytes (six anti-Hermitian
+ * colour matrices per site, 9 reals each).
  *
  * Spinor layout: field[p][3*spin + colour][V/2] complex (T re, T im), parity p and
  * checkerboard index as for links; sym_pack_spinor / sym_unpack_spinor convert from / to
@@ -224,8 +226,8 @@ int sym_set_coeffs_override(const double c[3]);
  * staples of each link (181 SU(3) products per link) and makes no assumption on the
  * matrices; SYM_ALG_FACTORED first forms the 6 plaquette staples of every link in the
  * workspace and builds rectangles and cube loops from them (63 products per link); it
- * stores each staple as two rows and rebuilds the third, which requires the links to
- * be special unitary to working precision (as the paper's link variables are, and as
+ * reads links and stores staples as two rows and rebuilds the third, which requires
+ * the links to be special unitary to working precision (as the paper's link variables are, and as
  * md_leapfrog keeps them). SYM_ALG_AUTO (default) is SYM_ALG_FACTORED.
  * SYM_EINVAL for other values.
  */

@@ -389,8 +389,8 @@ int do_fat_force(const Geom& g, const sym::fat::FatCoeffs& c, const void* U, con
 }
 
 size_t wilson_ws(const Geom& g, int prec) {
-  const size_t cxb = prec == SYM_F64 ? 2 * sizeof(double) : 2 * sizeof(float);
-  return align256((size_t)2 * 6 * 9 * cxb * (size_t)g.Vh);
+  const size_t rb = prec == SYM_F64 ? sizeof(double) : sizeof(float);
+  return align256((size_t)2 * 6 * 9 * rb * (size_t)g.Vh);  // six anti-Hermitian matrices per site
 }
 
 }  // namespace

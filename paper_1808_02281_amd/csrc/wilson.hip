@@ -24,8 +24,12 @@
 // sigma = +-1 as the plaquette's sense rho -> nu_s agrees with the leaf sense min -> max.
 // 9 products per plaquette, 56 per link with U B' and C' U^+.
 //
-// Spinor layout: field[p][3*spin + colour][V/2] complex (parity p, checkerboard cb);
-// clover insertions K[p][pair][9][V/2], pair = (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+// Spinor layout: field[p][3*spin + colour][V/2] complex (parity p, checkerboard cb).
+// Clover insertions, pair = (0,1),(0,2),(0,3),(1,2),(1,3),(2,3): K is anti-Hermitian,
+// so each is stored in 9 reals, block K[p][pair] of 9 V/2 reals = complex planes
+// K01, K02, K12, (Im K00, Im K11), then a real plane Im K22; half the bytes of a full
+// matrix on both sides (the force kernel reads 24 of them per link). Links are read as
+// their first two rows, the third rebuilt (special unitary).
 // Gamma matrices: Hermitian, DeGrand-Rossi basis, g_1..g_4 along x, y, z, t.
 #include "kernels.hpp"
 
@@ -139,6 +143,68 @@ __device__ __forceinline__ spinor<T> load_spinor(const T* F, int p, int Vh, int 
 
 constexpr int pair_index(int lo, int hi) { return lo == 0 ? hi - 1 : (lo == 1 ? hi + 1 : 5); }
 
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t antiherm_rsrc(const T* blk, int Vh) {
+  const unsigned bytes = 9u * (unsigned)Vh * (unsigned)sizeof(T);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(blk), (short)0, (int)bytes, kBufferWord3);
+}
+
+// the anti-Hermitian k into its 9-real block (layout above)
+template <typename T>
+__device__ __forceinline__ void store_antiherm(T* blk, int Vh, int cb, const su3<T>& k) {
+  const __amdgpu_buffer_rsrc_t r = antiherm_rsrc(static_cast<const T*>(blk), Vh);
+  const cx<T> v[4] = {k.e[1], k.e[2], k.e[5], cx<T>{k.e[0].im, k.e[4].im}};
+  const int voff = cb * (int)sizeof(cx<T>);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int soff = (int)((unsigned)c * (unsigned)Vh * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v[c]),
+                                            r, voff, soff, kStoreNT);
+    else
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v[c]),
+                                             r, voff, soff, kStoreNT);
+  }
+  const int voff1 = cb * (int)sizeof(T), soff1 = (int)(8u * (unsigned)Vh * (unsigned)sizeof(T));
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, k.e[8].im), r, voff1, soff1, kStoreNT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, k.e[8].im),
+                                          r, voff1, soff1, kStoreNT);
+}
+
+template <typename T>
+__device__ __forceinline__ su3<T> load_antiherm(const T* blk, int Vh, int cb) {
+  const __amdgpu_buffer_rsrc_t r = antiherm_rsrc(blk, Vh);
+  const int voff = cb * (int)sizeof(cx<T>);
+  cx<T> v[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int soff = (int)((unsigned)c * (unsigned)Vh * (unsigned)sizeof(cx<T>));
+    if constexpr (sizeof(T) == 4)
+      v[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+      v[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+  const int voff1 = cb * (int)sizeof(T), soff1 = (int)(8u * (unsigned)Vh * (unsigned)sizeof(T));
+  T d2;
+  if constexpr (sizeof(T) == 4)
+    d2 = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff1, soff1, 0));
+  else
+    d2 = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff1, soff1, 0));
+  su3<T> k;
+  k.e[0] = cx<T>{T(0), v[3].re};
+  k.e[1] = v[0];
+  k.e[2] = v[1];
+  k.e[3] = cx<T>{-v[0].re, v[0].im};
+  k.e[4] = cx<T>{T(0), v[3].im};
+  k.e[5] = v[2];
+  k.e[6] = cx<T>{-v[1].re, v[1].im};
+  k.e[7] = cx<T>{-v[2].re, v[2].im};
+  k.e[8] = cx<T>{T(0), d2};
+  return k;
+}
+
 // pass 1: K^{mu nu} = S - S^+, S = sum_a ([g_mu, g_nu] X)_a (x) Y_a^+, for every site
 template <typename T>
 __global__ __launch_bounds__(kBlock) void wilson_clover_kernel(Geom g, const T* __restrict__ X,
@@ -170,8 +236,7 @@ __global__ __launch_bounds__(kBlock) void wilson_clover_kernel(Geom g, const T* 
           const cx<T> sij = S.e[3 * i + j], sji = S.e[3 * j + i];
           k.e[3 * i + j] = cx<T>{sij.re - sji.re, sij.im + sji.im};
         }
-      cx<T>* blk = reinterpret_cast<cx<T>*>(K) + (size_t)((p * 6 + pair_index(mu, nu)) * 9) * (size_t)g.Vh;
-      store_link(blk, g.Vh, cb, k);
+      store_antiherm(K + (size_t)((p * 6 + pair_index(mu, nu)) * 9) * (size_t)g.Vh, g.Vh, cb, k);
     }
 }
 
@@ -187,13 +252,12 @@ struct WCtx {
   template <int D0, int D1, int D2, int D3, int A>
   __device__ __forceinline__ su3<T> u() const {
     constexpr int dp = offset_parity<D0, D1, D2, D3>();
-    return load_link(block_ptr(U, ax[A], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
+    return load_su3_rows(block_ptr(U, ax[A], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
   }
   template <int D0, int D1, int D2, int D3>
   __device__ __forceinline__ su3<T> k(int pair) const {
     constexpr int dp = offset_parity<D0, D1, D2, D3>();
-    const cx<T>* blk = reinterpret_cast<const cx<T>*>(K) + (size_t)((((p ^ dp) * 6) + pair) * 9) * (size_t)Vh;
-    return load_link(blk, Vh, nbr_cb<D0, D1, D2, D3>(nb));
+    return load_antiherm(K + (size_t)((((p ^ dp) * 6) + pair) * 9) * (size_t)Vh, Vh, nbr_cb<D0, D1, D2, D3>(nb));
   }
 };
 

@@ -148,7 +148,7 @@ def test_fat_validation(L_):
 
 def test_wilson_validation(L_):
     ok = _dims(4, 4, 4, 4)
-    assert L_.sym_wilson_workspace_bytes(ok, 1) >= 2 * 6 * 9 * 128 * 8
+    assert L_.sym_wilson_workspace_bytes(ok, 1) >= 2 * 6 * 9 * 128 * 4
     assert L_.sym_wilson_workspace_bytes(_dims(4, 4, 5, 4), 1) == 0
     w = L_.sym_wilson_force
     assert w(ok, 1, math.nan, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, HUGE, None) == -1
