@@ -35,10 +35,13 @@
 // reduction (kind 2) in action.hip.
 //
 // Staple storage: S8[mu][p][slot][6][V/2 + pad] complex, slot = 2*axis(e) + (e < 0);
-// the two slots with axis(e) = mu are never touched. A staple is a product of three
-// SU(3) links, hence itself in SU(3): only its first two rows are stored and the third
-// is rebuilt on load (lattice.hpp), which cuts the staple traffic by a third. This
-// relies on the links being special unitary to working precision.
+// the two slots with axis(e) = mu are never touched. In FP32 the six element planes of
+// a block are stored as three planes of element pairs (e[2q], e[2q+1]), 16 bytes per
+// site, so that a staple is three 16-byte loads per lane instead of six 8-byte ones.
+// A staple is a product of three SU(3) links, hence itself in SU(3): only its first two
+// rows are stored and the third is rebuilt on load (lattice.hpp), which cuts the staple
+// traffic by a third. This relies on the links being special unitary to working
+// precision.
 #pragma once
 
 #include "kernels.hpp"
@@ -87,6 +90,16 @@ __device__ __forceinline__ su3<T> full(const Rows2<T>& r) {
   return u;
 }
 
+// Two adjacent complex elements: the unit of the FP32 staple loads and stores. Whole
+// 16-byte buffer-load results are bit-cast into it: indexing the builtin's vector
+// result element by element was compiled into a single dword load whose value stood
+// for all four elements.
+template <typename T>
+struct CxPair {
+  cx<T> a, b;
+};
+using U32x4 = __attribute__((ext_vector_type(4))) unsigned;
+
 template <typename T>
 struct FCtx {
   const T* U;
@@ -124,15 +137,24 @@ struct FCtx {
     const unsigned bytes = 6u * (unsigned)Ss * (unsigned)sizeof(cx<T>);
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(blk), (short)0, (int)bytes, kBufferWord3);
-    const int voff = nbr_cb<D0, D1, D2, D3>(nb) * (int)sizeof(cx<T>);
     Rows2<T> u;
+    if constexpr (sizeof(T) == 4) {
+      // element pairs (e[2q], e[2q+1]): three 16-byte loads per lane
+      const int voff = nbr_cb<D0, D1, D2, D3>(nb) * (int)(2 * sizeof(cx<T>));
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const int soff = (int)((unsigned)c * (unsigned)Ss * (unsigned)sizeof(cx<T>));
-      if constexpr (sizeof(T) == 4)
-        u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-      else
+      for (int q = 0; q < 3; ++q) {
+        const int soff = (int)((unsigned)q * (unsigned)Ss * (unsigned)(2 * sizeof(cx<T>)));
+        const CxPair<T> v = __builtin_bit_cast(CxPair<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        u.e[2 * q] = v.a;
+        u.e[2 * q + 1] = v.b;
+      }
+    } else {
+      const int voff = nbr_cb<D0, D1, D2, D3>(nb) * (int)sizeof(cx<T>);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int soff = (int)((unsigned)c * (unsigned)Ss * (unsigned)sizeof(cx<T>));
         u.e[c] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+      }
     }
     return u;
   }
@@ -140,11 +162,7 @@ struct FCtx {
   // S(x+d, axis[AX], e) for e = sign ES along frame axis EAX
   template <int D0, int D1, int D2, int D3, int AX, int EAX, int ES>
   __device__ __forceinline__ su3<T> stap() const {
-    constexpr int dp = offset_parity<D0, D1, D2, D3>();
-    const int slot = 2 * axis[EAX] + (ES < 0 ? 1 : 0);
-    const cx<T>* blk = reinterpret_cast<const cx<T>*>(S8) +
-                       (size_t)((((axis[AX] * 2) + (p ^ dp)) * 8 + slot) * 6) * (size_t)Ss;
-    return load_su3_rows(blk, Ss, nbr_cb<D0, D1, D2, D3>(nb));
+    return full(stap_rows<D0, D1, D2, D3, AX, EAX, ES>());
   }
 };
 
@@ -179,7 +197,19 @@ __device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
     const su3<T> s = plaquette_staple<T, J>(lc);
     const int slot = 2 * c.axis[e_axis(J)] + (e_sign(J) < 0 ? 1 : 0);
     cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((c.axis[0] * 2 + c.p) * 8 + slot) * 6) * (size_t)c.Ss;
-    store_su3_rows(dst, c.Ss, cb, s);
+    if constexpr (sizeof(T) == 4) {
+      const unsigned bytes = 6u * (unsigned)c.Ss * (unsigned)sizeof(cx<T>);
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)bytes, kBufferWord3);
+      const int voff = cb * (int)(2 * sizeof(cx<T>));
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int soff = (int)((unsigned)q * (unsigned)c.Ss * (unsigned)(2 * sizeof(cx<T>)));
+        const CxPair<T> v{s.e[2 * q], s.e[2 * q + 1]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), r, voff, soff, kStoreNT);
+      }
+    } else {
+      store_su3_rows(dst, c.Ss, cb, s);
+    }
     SYM_FENCE();
     write_staples<T, J + 1>(c, S8, cb);
   }
