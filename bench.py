@@ -31,7 +31,7 @@ FLOP_STAPLES = 2376         # factored pass 1: 6 plaquette staples x 2 products
 FLOP_FACTORED = 11494       # factored pass 2: 51 products + sums, traces, TA
 FLOP_DIRECT = 36940         # direct kernel: 181 products + sums, traces, TA
 # Minimum HBM bytes per link of each kernel (read once / write once), per real size r.
-BYTES_STAPLES = lambda r: (18 + 6 * 12) * r              # read U, write 6 two-row staples
+BYTES_STAPLES = lambda r: (12 + 6 * 12) * r              # read U (two rows), write 6 two-row staples
 BYTES_FACTORED = lambda r: (18 + 6 * 12 + 18) * r        # read U and own staples, write G
 BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 
@@ -44,12 +44,12 @@ FAT_FLOP = {"fat_fk1": 2754, "fat_fk2": 7722, "fat_fk3": 2916, "fat_bk3": 2538, 
 FAT_MATRICES = {"fat_fk1": 4, "fat_fk2": 10, "fat_fk3": 9, "fat_bk3": 5, "fat_bk2": 12, "fat_gk": 22}
 C_ASQTAD = (5 / 8, -1 / 16, 1 / 64, -1 / 384, -1 / 16, -1 / 24)
 
-# Wilson-clover force, flop per link (force kernel: 6 clover plaquettes of 9 products
+# Wilson-clover force, flop per link (force kernel: 6 clover plaquettes of 8 products
 # each with the insertions, hopping outer products, U B' and C' U^+, TA) and per link of
 # the clover-insertion pass (6 colour matrices per site from X, Y); minimum bytes per
 # link in reals: force = U (two rows) + G + a quarter of the site's X, Y (24 complex) and
 # K (six anti-Hermitian matrices, 9 reals each).
-WILSON_FLOP = {"wilson_force": 12450, "wilson_clover": 500}
+WILSON_FLOP = {"wilson_force": 11262, "wilson_clover": 500}
 WILSON_REALS = {"wilson_force": 12 + 18 + (48 + 54) / 4, "wilson_clover": (48 + 54) / 4}
 KAPPA, CSW = 0.1242, 1.37
 

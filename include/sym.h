@@ -120,16 +120,17 @@ int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, v
 /*
  * Batched force: the forces (and optionally the actions) of n independent lattices of
  * any valid shapes, sharing u0, beta and prec, with one launch per pass for every 64
- * lattices: persistent workgroups walk the concatenated link tiles of all lattices with
- * a static schedule, so the result does not depend on timing and each link's force is
- * the same as sym_force's with SYM_ALG_FACTORED. The work table is passed by value in
+ * lattices: workgroups walk the concatenated link tiles of all lattices with a static
+ * schedule (one tile per workgroup, or a persistent grid that loops over tiles), so the
+ * result does not depend on timing and each link's force is the same as sym_force's
+ * with SYM_ALG_FACTORED. The work table is passed by value in
  * the kernel arguments, so a call may be captured into a HIP graph (with the same
  * workspace) and replayed. L: host array of n x 4 dims. U, F: host arrays of n device
  * pointers (fields as in sym_force). S_dev: NULL or 4n device doubles, {S, W_P, W_R, W_C}
  * per lattice. ws: at least sym_batch_workspace_bytes(n, L, prec) bytes (0 if invalid).
- * The schedule (number of persistent workgroups, tile order) is the one
- * sym_batch_autotune chose for these shapes and precision in this process, else a
- * default of one resident wave of workgroups with an XCD-contiguous order.
+ * The schedule (number of persistent workgroups, or one workgroup per tile; tile
+ * order) is the one sym_batch_autotune chose for these shapes and precision in this
+ * process, else one workgroup per tile in an XCD-contiguous order.
  */
 size_t sym_batch_workspace_bytes(int n, const int32_t* L, int prec);
 int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
@@ -137,10 +138,12 @@ int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, c
 
 /*
  * Autotuner for sym_force_batch: times every candidate schedule (256..4096 persistent
- * workgroups x two tile orders) on the caller's fields (F is overwritten), synchronising
- * the stream, keeps the fastest for later calls with the same shapes and precision
- * (in-process cache), and returns it through grid_out / order_out (nullable). Not for
- * use under graph capture.
+ * workgroups, or one workgroup per tile, reported as grid 0; x two tile orders) on the
+ * caller's fields (F is overwritten: it ends with the forces of the last schedule
+ * timed, 256 persistent workgroups in XCD-contiguous order), synchronising the stream,
+ * keeps the fastest for later calls with the same shapes and precision (in-process
+ * cache), and returns it through grid_out / order_out (nullable). Not for use under
+ * graph capture.
  */
 int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
                        void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out);

@@ -242,13 +242,20 @@ def force_batch(Us, Ls, u0, beta, with_action=False, out=None, S_out=None):
     return (Fs, S) if with_action else Fs
 
 
-def batch_autotune(Us, Ls, u0, beta):
+def batch_autotune(Us, Ls, u0, beta, out=None):
     """Time the candidate schedules of force_batch for this batch; the best one is kept
-    for later force_batch calls with the same lattice shapes. Returns (grid, order)."""
+    for later force_batch calls with the same lattice shapes. Returns (grid, order);
+    grid 0 is one workgroup per tile. ``out`` (optional, one field per lattice) receives
+    the forces of the last schedule timed (256 persistent workgroups)."""
     n, Lflat, prec = _batch_args(Us, Ls)
     dev = Us[0].device
     ws = batch_workspace(Ls, prec, dev)
-    Fs = [torch.empty_like(U) for U in Us]
+    Fs = [torch.empty_like(U) for U in Us] if out is None else out
+    if len(Fs) != n:
+        raise ValueError("out needs one field per lattice")
+    for U, F in zip(Us, Fs):
+        if F.shape != U.shape or F.dtype != U.dtype or not F.is_contiguous():
+            raise ValueError("out fields must match U in shape and dtype and be contiguous")
     Up = (ctypes.c_void_p * n)(*[U.data_ptr() for U in Us])
     Fp = (ctypes.c_void_p * n)(*[F.data_ptr() for F in Fs])
     grid, order = ctypes.c_int32(), ctypes.c_int32()

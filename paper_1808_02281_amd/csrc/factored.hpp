@@ -218,22 +218,6 @@ __device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
 
 // ---------------------------------------------------------------- pass 2
 
-// Long-side rectangles: RA += S(x+mu,mu,e) S(x,mu,e), RB += S(x,mu,e) S(x-mu,mu,e), tP += S(x,mu,e).
-template <typename T, int J>
-__device__ __forceinline__ void long_side(const FCtx<T>& c, su3<T>& tP, su3<T>& RA, su3<T>& RB) {
-  if constexpr (J < 6) {
-    FCtx<T> lc = c;
-    launder(lc);
-    constexpr int a = e_axis(J), s = e_sign(J);
-    const su3<T> sx = lc.template stap<0, 0, 0, 0, 0, a, s>();
-    add(tP, sx);
-    mac<false, false>(RA, lc.template stap<1, 0, 0, 0, 0, a, s>(), sx);
-    mac<false, false>(RB, sx, lc.template stap<-1, 0, 0, 0, 0, a, s>());
-    SYM_FENCE();
-    long_side<T, J + 1>(c, tP, RA, RB);
-  }
-}
-
 // Short-side rectangles and cube loops, software-pipelined. For e = e_J (J = 0..5) and
 // the four f perpendicular to mu and e (cube_f(J, i)):
 //   t += U_{x+mu,e} [ c_R S(x+e,mu,e) U_{x,e}^dag + c_C sum_f S(x+e,mu,f) S'(x,e,f) ].
@@ -243,7 +227,9 @@ __device__ __forceinline__ void long_side(const FCtx<T>& c, su3<T>& tP, su3<T>& 
 // arithmetic instead of by other waves alone (FP32, 32^3 x 64 force pass: 3.26 ms in
 // plain order, 3.11 ms with the cube loop pipelined, 3.08 ms with the long-side sums
 // pipelined too, 223 VGPRs; issuing the first cube loads during the long-side epilogue
-// as well reached 256 VGPRs and was slower).
+// as well reached 256 VGPRs and was slower). FP64 takes the same form: its operands
+// need about 420 registers, so one wave per SIMD holds them in VGPRs and AGPRs
+// (6.72 ms in plain order, 6.50 ms pipelined).
 constexpr int cube_f(int J, int i) {
   int n = 0;
   for (int K = 0; K < 6; ++K) {
@@ -381,59 +367,9 @@ __device__ __forceinline__ void cubes_pipe(const FCtx<T>& c, su3<T>& t, const Cu
 }
 
 
-// The same sums in plain order (one e after the other, loads just before their use):
-// FP64 uses this form; the pipelined one needs twice the registers for its operands
-// and measured slower in FP64 (one wave per SIMD either way).
-template <typename T, int J, int K>
-__device__ __forceinline__ void cube_sum(const FCtx<T>& c, su3<T>& Q) {
-  if constexpr (K < 6) {
-    constexpr int a = e_axis(J), s = e_sign(J), fa = e_axis(K), fs = e_sign(K);
-    if constexpr (fa != a) {
-      constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
-      const su3<T> left = c.template stap<0, e1, e2, e3, 0, fa, fs>();
-      if constexpr (s > 0) {
-        mac<false, false>(Q, left, c.template stap<0, 0, 0, 0, a, fa, fs>());
-      } else {
-        mac<false, true>(Q, left, c.template stap<0, e1, e2, e3, a, fa, fs>());
-      }
-    }
-    cube_sum<T, J, K + 1>(c, Q);
-  }
-}
-
-template <typename T, int J>
-__device__ __forceinline__ void short_side_and_cubes_serial(const FCtx<T>& c, su3<T>& t, T cR, T cC) {
-  if constexpr (J < 6) {
-    FCtx<T> lc = c;
-    launder(lc);
-    constexpr int a = e_axis(J), s = e_sign(J);
-    constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
-    su3<T> Q;
-    set_zero(Q);
-    cube_sum<T, J, 0>(lc, Q);
-    su3<T> R;
-    if constexpr (s > 0) {
-      R = mul<false, true>(lc.template stap<0, e1, e2, e3, 0, a, s>(), lc.template link<0, 0, 0, 0, a>());
-    } else {
-      R = mul<false, false>(lc.template stap<0, e1, e2, e3, 0, a, s>(), lc.template link<0, e1, e2, e3, a>());
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      R.e[i].re = fma(cC, Q.e[i].re, cR * R.e[i].re);
-      R.e[i].im = fma(cC, Q.e[i].im, cR * R.e[i].im);
-    }
-    if constexpr (s > 0) {
-      mac<false, false>(t, lc.template link<1, 0, 0, 0, a>(), R);
-    } else {
-      mac<true, false>(t, lc.template link<1, e1, e2, e3, a>(), R);
-    }
-    SYM_FENCE();
-    short_side_and_cubes_serial<T, J + 1>(c, t, cR, cC);
-  }
-}
-
-// Long-side rectangles, software-pipelined (FP32): the three staples of e_{J+1} are
-// requested before those of e_J are multiplied out.
+// Long-side rectangles, RA += S(x+mu,mu,e) S(x,mu,e), RB += S(x,mu,e) S(x-mu,mu,e),
+// tP += S(x,mu,e), software-pipelined: the three staples of e_{J+1} are requested
+// before those of e_J are multiplied out.
 template <typename T>
 struct LongSide {
   Rows2<T> sx, sp, sm;  // S(x,mu,e), S(x+mu,mu,e), S(x-mu,mu,e)
@@ -505,13 +441,9 @@ __device__ __forceinline__ void factored_link(const Geom& g, const T* U, const T
     set_zero(tP);
     set_zero(RA);
     set_zero(RB);
-    if constexpr (sizeof(T) == 4) {
-      const LongSide<T> d0 = load_long<0>(c);
-      SYM_FENCE();
-      long_pipe<0>(c, tP, RA, RB, d0);
-    } else {
-      long_side<T, 0>(c, tP, RA, RB);
-    }
+    const LongSide<T> d0 = load_long<0>(c);
+    SYM_FENCE();
+    long_pipe<0>(c, tP, RA, RB, d0);
     SYM_FENCE();
     FCtx<T> lc = c;
     launder(lc);
@@ -528,14 +460,12 @@ __device__ __forceinline__ void factored_link(const Geom& g, const T* U, const T
     part = re_tr_mul(u, t);
   }
   SYM_FENCE();
-  if constexpr (sizeof(T) == 4) {
-    // FP32: software-pipelined short-side rectangles and cube loops
+  {
+    // software-pipelined short-side rectangles and cube loops
     const CubeA<T> a0 = load_cube_a<0>(c);
     const CubeB<T> b0 = load_cube_b<0>(c);
     SYM_FENCE();
     cubes_pipe<0>(c, t, a0, b0, cR, cC);
-  } else {
-    short_side_and_cubes_serial<T, 0>(c, t, cR, cC);
   }
 
   FCtx<T> lc = c;

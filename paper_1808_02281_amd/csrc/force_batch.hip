@@ -1,8 +1,9 @@
 // Batched factored force: many independent lattices (uneven sizes) in one launch per
-// pass. Persistent workgroups walk the concatenated tiles of all lattices with a
-// static schedule (no atomics: the result, including the action partials, does not
-// depend on timing) and run the same per-link code as the single-lattice kernels
-// (factored.hpp), so every link's force is bitwise the single-lattice one.
+// pass. Workgroups walk the concatenated tiles of all lattices with a static schedule
+// (one tile each when the grid covers every tile, else a persistent loop; no atomics:
+// the result, including the action partials, does not depend on timing) and run the
+// same per-link code as the single-lattice kernels (factored.hpp), so every link's
+// force is bitwise the single-lattice one.
 #include "factored.hpp"
 
 namespace sym {

@@ -47,7 +47,8 @@ hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out,
   const int nt = factored_tiles(g);
   // Occupancy cap through an LDS reservation (the kernel uses none): fewer resident
   // waves keep more of each wave's staple reads in L2. Measured on the 32^3 x 64
-  // workload: 2 waves per SIMD for FP32 (3 by registers alone), 1 for FP64 (2).
+  // workload: 2 waves per SIMD for FP32, 1 for FP64, which is also where the
+  // software-pipelined forms land by their register counts alone.
   const size_t lds = factored_lds_reservation<T>();
   if (mode == ForceOut::Store)
     force_factored_kernel<T, ForceOut::Store><<<nt, kBlock, lds, s>>>(g, U, S8, out, kick, partials, c, nt);

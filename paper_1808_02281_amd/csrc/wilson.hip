@@ -22,7 +22,8 @@
 //   M_clov = -(c_sw kappa / 8) U sum_{nu, s} sigma (abd K_c0 + K_c1 abd + a K_c2 bd + ab K_c3 d),
 // with a = U_{k+rho,nu_s}, b = U_{k+rho+nu_s,-rho}, d = U_{k+nu_s,-nu_s}, and
 // sigma = +-1 as the plaquette's sense rho -> nu_s agrees with the leaf sense min -> max.
-// 9 products per plaquette, 56 per link with U B' and C' U^+.
+// The last two terms share their outer factors, a (K_c2 b + b K_c3) d: 8 products per
+// plaquette, 50 per link with U B' and C' U^+.
 //
 // Spinor layout: field[p][3*spin + colour][V/2] complex (parity p, checkerboard cb).
 // Clover insertions, pair = (0,1),(0,2),(0,3),(1,2),(1,3),(2,3): K is anti-Hermitian,
@@ -291,13 +292,13 @@ __device__ __forceinline__ void clover_plaquette(su3<T>& acc, const WCtx<T>& c0)
     d = c.template u<0, -e1, -e2, -e3, J>();
   }
   const su3<T> b = dagger(c.template u<0, f1, f2, f3, 0>());
-  const su3<T> ab = mul<false, false>(a, b);
-  const su3<T> bd = mul<false, false>(b, d);
-  const su3<T> abd = mul<false, false>(ab, d);
+  const su3<T> abd = mul<false, false>(mul<false, false>(a, b), d);
   su3<T> t = mul<false, false>(abd, c.template k<0, 0, 0, 0>(pair));
   mac<false, false>(t, c.template k<1, 0, 0, 0>(pair), abd);
-  mac<false, false>(t, mul<false, false>(a, c.template k<1, f1, f2, f3>(pair)), bd);
-  mac<false, false>(t, mul<false, false>(ab, c.template k<0, f1, f2, f3>(pair)), d);
+  // a K2 b d + a b K3 d = a (K2 b + b K3) d
+  su3<T> x = mul<false, false>(c.template k<1, f1, f2, f3>(pair), b);
+  mac<false, false>(x, b, c.template k<0, f1, f2, f3>(pair));
+  mac<false, false>(t, mul<false, false>(a, x), d);
   axpy(acc, sigma, t);
 }
 

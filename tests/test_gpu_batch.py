@@ -67,14 +67,20 @@ def test_batch_larger_than_one_launch(sym):
         assert abs(S[i, 0].item() - S1[0].item()) <= 1e-12 * abs(S1[0].item())
 
 
-def test_autotune_keeps_results(sym):
-    Us = _fields(SHAPES, "f32", seed0=7)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autotune_keeps_results(sym, prec):
+    """The default schedule is one workgroup per tile; the autotuner's last candidate is
+    a persistent grid (256 workgroups, each looping over two or three of the 592 tiles):
+    both, and the schedule it keeps, give bitwise the same forces."""
+    Us = _fields(SHAPES, prec, seed0=7)
     F0 = sym.force_batch(Us, SHAPES, U0, BETA)
-    grid, order = sym.batch_autotune(Us, SHAPES, U0, BETA)
-    assert grid in (256, 512, 768, 1024, 1536, 2048, 3072, 4096) and order in (0, 1)
+    Fp = [torch.empty_like(U) for U in Us]
+    grid, order = sym.batch_autotune(Us, SHAPES, U0, BETA, out=Fp)
+    assert grid in (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096) and order in (0, 1)
     F1 = sym.force_batch(Us, SHAPES, U0, BETA)
-    for a, b in zip(F0, F1):
+    for a, b, c in zip(F0, F1, Fp):
         assert torch.equal(a, b)
+        assert torch.equal(a, c)
 
 
 def test_graph_replay_matches_eager(sym):
