@@ -326,8 +326,9 @@ def bench_wilson(sym, torch, U_np, L, steps, warmup, with_fp64=True, with_cpu=Tr
 
 def bench_autograd(sym, torch, gaugegen, u0, beta, steps, warmup):
     """Differentiation on the 24^3x48 workload (links eps 0.3, seed 3): S_G through
-    torch autograd, forward = action kernel, backward = force kernels (2 G U per link);
-    one step = forward + backward."""
+    torch autograd, forward = force kernels with the fused action (2 G U per link kept
+    for the backward), backward = scaling by the incoming gradient; one step = forward
+    + backward."""
     cfg = gaugegen.CONFIGS["thermal_24x24x24x48"]
     L = cfg["L"]
     dev = torch.device("cuda:0")

@@ -1,8 +1,9 @@
 """Differentiable access to the Symanzik action.
 
 ``symanzik_action(U, L, u0, beta)`` returns S_G (a 0-d float64 CUDA tensor) for a link
-field in the SoA even-odd layout; its backward runs the force kernels
-(sym_action_grad), which return 2 G U per link: the gradient of S_G with respect to
+field in the SoA even-odd layout; its gradient comes from the force kernels
+(sym_action_grad, run in the forward when a backward can follow), which return 2 G U
+per link: the gradient of S_G with respect to
 the link matrices, projected on the tangent space of SU(3) at U. Derivatives along
 any parametrisation that keeps the links in SU(3) -- for instance
 U = exp(i omega.T) U0 built with torch ops -- are therefore exact, and
@@ -43,18 +44,24 @@ class _Unpack(torch.autograd.Function):
 
 
 class SymanzikAction(torch.autograd.Function):
+    """S_G(U). When a backward can follow, the forward runs the force kernels once
+    (sym_action_grad with the fused action: S from the same staple sums) and keeps
+    2 G U for the backward; otherwise it runs the action kernel alone."""
+
     @staticmethod
-    def forward(ctx, U, L, u0, beta):
-        ctx.save_for_backward(U)
-        ctx.args = (tuple(L), float(u0), float(beta))
-        return api.action(U, ctx.args[0], u0, beta)[0]
+    def forward(ctx, U, L, u0, beta, with_grad):
+        L = tuple(L)
+        if with_grad:
+            grad, S = api.action_grad(U, L, u0, beta, with_action=True)
+            ctx.save_for_backward(grad)
+            return S[0]
+        ctx.save_for_backward(None)
+        return api.action(U, L, u0, beta)[0]
 
     @staticmethod
     def backward(ctx, gS):
-        (U,) = ctx.saved_tensors
-        L, u0, beta = ctx.args
-        grad = api.action_grad(U, L, u0, beta)
-        return grad * gS.to(grad.dtype), None, None, None
+        (grad,) = ctx.saved_tensors
+        return grad * gS.to(grad.dtype), None, None, None, None
 
 
 def pack(aos, L):
@@ -66,7 +73,7 @@ def unpack(soa, L):
 
 
 def symanzik_action(U, L, u0, beta):
-    return SymanzikAction.apply(U, L, u0, beta)
+    return SymanzikAction.apply(U, L, u0, beta, torch.is_grad_enabled() and U.requires_grad)
 
 
 class FatSmear(torch.autograd.Function):

@@ -102,3 +102,26 @@ def test_gradient_at_zero_matches_oracle_24x24x24x48(sym, dtype, tol):
     err = np.abs(d_gpu - d_ref).max() / np.abs(d_ref).max()
     print(f"  {dtype}: max |dS/domega - oracle| / max |oracle| = {err:.2e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-6)])
+def test_forward_value_with_and_without_grad(sym, dtype, tol):
+    """With a backward possible the forward takes S from the force kernels' fused
+    action; without, from the action kernel: the same S (and the oracle's)."""
+    from paper_1808_02281_amd import autograd as ag
+
+    L = (6, 6, 6, 8)
+    U = gaugegen.near_thermal_links(L, 0.3, 23)
+    Us = ag.pack(torch.from_numpy(U).to(dtype).to(device()), L)
+    with torch.no_grad():
+        s0 = ag.symanzik_action(Us, L, U0, BETA).item()
+    x = Us.clone().requires_grad_(True)
+    S = ag.symanzik_action(x, L, U0, BETA)
+    s1 = S.item()
+    S.backward()
+    Ur = U if dtype == torch.complex128 else U.astype(np.complex64).astype(np.complex128)
+    c, _ = oracle.coeffs(U0)
+    s_ref = oracle.action(Ur, L, c, BETA)[0]
+    assert abs(s1 - s0) <= tol * abs(s0)
+    assert abs(s1 - s_ref) <= tol * abs(s_ref)
+    assert x.grad is not None and torch.isfinite(x.grad).all()
