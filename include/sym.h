@@ -175,10 +175,16 @@ int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec
  *                       with dPhi/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U:
  *                       the same convention as the gauge force G of sym_force, so the
  *                       two add.
+ *   flag SYM_FAT_REUSE_LINKS (or-ed into the mode): ws already holds the forward
+ *                       intermediates of a sym_fat_links call with the same L, prec, c
+ *                       and U, made on this stream with no other use of ws since; the
+ *                       two forward passes are then skipped (the caller vouches for
+ *                       this: it cannot be checked). Other mode values: SYM_EINVAL.
  * ws: at least sym_fat_workspace_bytes(L, prec) bytes (19 matrices per link of
- * intermediate fields). Errors and asynchrony as for sym_force.
+ * intermediate fields, of which sym_fat_links leaves 9 that the force reads).
+ * Errors and asynchrony as for sym_force.
  */
-typedef enum { SYM_FAT_GRAD = 0, SYM_FAT_FORCE = 1 } sym_fat_mode;
+typedef enum { SYM_FAT_GRAD = 0, SYM_FAT_FORCE = 1, SYM_FAT_REUSE_LINKS = 2 } sym_fat_mode;
 size_t sym_fat_workspace_bytes(const int32_t L[4], int prec);
 int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U, void* V, void* W, void* ws,
                   size_t ws_bytes, sym_stream_t stream);

@@ -19,6 +19,7 @@ from .api import (  # noqa: F401
     field_shape,
     force,
     md_leapfrog,
+    new_fat_workspace,
     pack,
     pack_spinor,
     profile_collect,

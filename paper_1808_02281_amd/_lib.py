@@ -42,6 +42,7 @@ EXPORTS = (
     "sym_unpack_spinor",
 )
 FAT_MODES = {"grad": 0, "force": 1}
+FAT_REUSE_LINKS = 2
 
 
 class SymError(RuntimeError):

@@ -288,14 +288,32 @@ def fat_workspace(L, prec, device):
     return ws
 
 
-def fat_links(U, L, c, with_naik=True, out=None):
+def new_fat_workspace(L, prec, device):
+    """A private (uncached) fat-link workspace, for keeping forward intermediates."""
+    n = int(_lib.lib().sym_fat_workspace_bytes(_lib.dims(L), int(prec)))
+    if n == 0:
+        raise ValueError(f"invalid lattice {tuple(L)} or precision {prec}")
+    return torch.empty(n, dtype=torch.uint8, device=torch.device(device))
+
+
+def _check_ws(ws, L, prec, device):
+    n = int(_lib.lib().sym_fat_workspace_bytes(_lib.dims(L), int(prec)))
+    if ws.dtype != torch.uint8 or ws.numel() < n or ws.device != torch.device(device) or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 device tensor of sym_fat_workspace_bytes bytes")
+
+
+def fat_links(U, L, c, with_naik=True, out=None, ws=None):
     """Asqtad/HISQ fat links V (and Naik links W) of a link field (sym_fat_links).
 
     c = (c_1, c_3, c_5, c_7, c_L, c_N). Returns V, or (V, W) with_naik; ``out`` may
-    give V or (V, W)."""
+    give V or (V, W). ``ws``: a workspace to use instead of the cached one (it then
+    holds the forward intermediates for fat_force(..., reuse_links=True))."""
     _check_field("U", U, L)
     prec = prec_of(U.dtype)
-    ws = fat_workspace(L, prec, U.device)
+    if ws is None:
+        ws = fat_workspace(L, prec, U.device)
+    else:
+        _check_ws(ws, L, prec, U.device)
     if out is None:
         V = torch.empty_like(U)
         W = torch.empty_like(U) if with_naik else None
@@ -310,10 +328,12 @@ def fat_links(U, L, c, with_naik=True, out=None):
     return (V, W) if with_naik else V
 
 
-def fat_force(U, L, c, GV, GW=None, mode="grad", out=None):
+def fat_force(U, L, c, GV, GW=None, mode="grad", out=None, ws=None, reuse_links=False):
     """Pull-back of the adjoint fields GV (of V) and GW (of W, optional) to the thin links
     (sym_fat_force): mode 'grad' gives dPhi/dRe U + i dPhi/dIm U, 'force' the traceless
-    antihermitian G = -(1/2)(U grad^+)_TA (gauge-force convention)."""
+    antihermitian G = -(1/2)(U grad^+)_TA (gauge-force convention). ``reuse_links``:
+    ``ws`` holds the intermediates of fat_links(U, L, c, ws=ws), so the forward passes
+    are skipped."""
     _check_field("U", U, L)
     _check_field("GV", GV, L)
     if GW is not None:
@@ -322,13 +342,18 @@ def fat_force(U, L, c, GV, GW=None, mode="grad", out=None):
         if t is not None and t.dtype != U.dtype:
             raise TypeError("adjoint fields must have the dtype of U")
     prec = prec_of(U.dtype)
-    ws = fat_workspace(L, prec, U.device)
+    if reuse_links and ws is None:
+        raise ValueError("reuse_links needs the workspace that fat_links filled")
+    if ws is None:
+        ws = fat_workspace(L, prec, U.device)
+    else:
+        _check_ws(ws, L, prec, U.device)
     o = torch.empty_like(U) if out is None else out
     _check_field("out", o, L)
+    m = _lib.FAT_MODES[mode] | (_lib.FAT_REUSE_LINKS if reuse_links else 0)
     _lib.check("sym_fat_force", _lib.lib().sym_fat_force(_lib.dims(L), prec, _fat_c(c), _ptr(U), _ptr(GV),
-                                                         _ptr(GW) if GW is not None else None, _ptr(o),
-                                                         _lib.FAT_MODES[mode], _ptr(ws), ws.numel(),
-                                                         _stream(U.device)))
+                                                         _ptr(GW) if GW is not None else None, _ptr(o), m,
+                                                         _ptr(ws), ws.numel(), _stream(U.device)))
     return o
 
 

@@ -77,13 +77,17 @@ def symanzik_action(U, L, u0, beta):
 
 
 class FatSmear(torch.autograd.Function):
-    """(V, W) = fat and Naik links of U; backward = the path-force kernels (sym_fat_force)."""
+    """(V, W) = fat and Naik links of U; backward = the path-force kernels (sym_fat_force).
+    When a backward can follow, the forward fills a private workspace that is kept
+    until the backward, which then reuses its intermediates (SYM_FAT_REUSE_LINKS)
+    instead of recomputing the two forward passes."""
 
     @staticmethod
-    def forward(ctx, U, L, c):
+    def forward(ctx, U, L, c, with_grad):
         ctx.save_for_backward(U)
         ctx.args = (tuple(L), tuple(float(v) for v in c))
-        return api.fat_links(U, ctx.args[0], ctx.args[1], with_naik=True)
+        ctx.ws = api.new_fat_workspace(ctx.args[0], api.prec_of(U.dtype), U.device) if with_grad else None
+        return api.fat_links(U, ctx.args[0], ctx.args[1], with_naik=True, ws=ctx.ws)
 
     @staticmethod
     def backward(ctx, gV, gW):
@@ -91,12 +95,16 @@ class FatSmear(torch.autograd.Function):
         L, c = ctx.args
         if gV is None:
             gV = torch.zeros_like(U)
-        grad = api.fat_force(U, L, c, gV.contiguous(), None if gW is None else gW.contiguous(), mode="grad")
-        return grad, None, None
+        gW = None if gW is None else gW.contiguous()
+        if ctx.ws is not None:
+            grad = api.fat_force(U, L, c, gV.contiguous(), gW, mode="grad", ws=ctx.ws, reuse_links=True)
+        else:
+            grad = api.fat_force(U, L, c, gV.contiguous(), gW, mode="grad")
+        return grad, None, None, None
 
 
 def fat_smear(U, L, c):
     """Differentiable asqtad/HISQ smearing: (V, W) with V the fat links and W the Naik
     links of the SoA link field U (real gradient layout as for the fields: the gradient
     of a real function with respect to the re and im parts of every element)."""
-    return FatSmear.apply(U, L, c)
+    return FatSmear.apply(U, L, c, torch.is_grad_enabled() and U.requires_grad)

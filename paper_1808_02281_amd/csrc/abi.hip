@@ -387,8 +387,10 @@ int do_fat_force(const Geom& g, const sym::fat::FatCoeffs& c, const void* U, con
   T* o = static_cast<T*>(out);
   static const char* names[5] = {"fat_fk1", "fat_fk2", "fat_bk3", "fat_bk2", "fat_gk"};
   hipError_t e = hipSuccess;
-  for (int stage = 0; stage < 5 && e == hipSuccess; ++stage)
-    e = timed(names[stage], s, [&] { return sym::launch_fat_stage<T>(stage, g, u, gv, gw, o, mode, c, w, s); });
+  // with SYM_FAT_REUSE_LINKS the workspace already holds what FK1 and FK2 write
+  const int first = (mode & SYM_FAT_REUSE_LINKS) ? 2 : 0, out_mode = mode & SYM_FAT_FORCE;
+  for (int stage = first; stage < 5 && e == hipSuccess; ++stage)
+    e = timed(names[stage], s, [&] { return sym::launch_fat_stage<T>(stage, g, u, gv, gw, o, out_mode, c, w, s); });
   return hip_status(e);
 }
 
@@ -605,7 +607,7 @@ int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U
   if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = fat_coeffs(c, &cf)) || (rc = check_ptr(U)) ||
       (rc = check_ptr(GV)) || (GW && (rc = check_ptr(GW))) || (rc = check_ptr(out)) || (rc = check_ptr(ws)))
     return rc;
-  if (mode != SYM_FAT_GRAD && mode != SYM_FAT_FORCE) return SYM_EINVAL;
+  if ((mode & ~(SYM_FAT_FORCE | SYM_FAT_REUSE_LINKS)) != 0) return SYM_EINVAL;
   if (ws_bytes < fat_ws_bytes(g, prec)) return SYM_EWORKSPACE;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return prec == SYM_F64 ? do_fat_force<double>(g, cf, U, GV, GW, out, mode, fat_carve<double>(ws, g, prec), s)

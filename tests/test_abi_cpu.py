@@ -139,7 +139,8 @@ def test_fat_validation(L_):
     assert fl(ok, 1, c, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
     assert fl(ok, 1, c, FAKE, FAKE, None, FAKE, 64, None) == -3
     ff = L_.sym_fat_force
-    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, 2, FAKE, HUGE, None) == -1   # mode
+    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, 4, FAKE, HUGE, None) == -1   # mode
+    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, -1, FAKE, HUGE, None) == -1
     assert ff(ok, 1, c, FAKE, None, None, FAKE, 0, FAKE, HUGE, None) == -2   # GV required
     assert ff(ok, 1, c, FAKE, FAKE, None, None, 0, FAKE, HUGE, None) == -2   # out required
     assert ff(ok, 3, c, FAKE, FAKE, None, FAKE, 0, FAKE, HUGE, None) == -1

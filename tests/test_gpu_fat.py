@@ -216,3 +216,22 @@ def test_graph_replay_matches_eager(sym):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, eager), f"replay {rep}"
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_reuse_of_forward_intermediates(sym, prec):
+    """fat_force with reuse_links on the workspace that fat_links filled gives bitwise
+    the result of the full call, in both output modes."""
+    L = (6, 6, 6, 8)
+    U, GV, GW = _inputs(L, 31, prec)
+    dev = device()
+    Us, GVs, GWs = (to_soa(sym, X, L, prec, dev) for X in (U, GV, GW))
+    ws = sym.new_fat_workspace(L, sym.prec_of(Us.dtype), dev)
+    for mode in ("grad", "force"):
+        full = sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, mode=mode)
+        sym.fat_links(Us, L, C_ASQTAD, ws=ws)
+        again = sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, mode=mode, ws=ws, reuse_links=True)
+        assert torch.equal(full, again), mode
+    with pytest.raises(ValueError):
+        sym.fat_force(Us, L, C_ASQTAD, GVs, GWs, reuse_links=True)
+
