@@ -216,16 +216,33 @@ int do_leapfrog(const Geom& g, const Coeffs& c, void* Uv, void* Pv, double dt, i
   T* U = static_cast<T*>(Uv);
   T* P = static_cast<T*>(Pv);
   hipError_t e = hipSuccess;
-  if (H_dev) e = hamiltonian<T>(g, c, U, P, H_dev, w, s);
-  if (nsteps > 0 && e == hipSuccess) e = force_into<T>(g, U, P, 0.5 * dt, nullptr, c, ForceOut::Kick, w, s);
+  if (nsteps == 0) {
+    if (H_dev) e = hamiltonian<T>(g, c, U, P, H_dev, w, s);
+    if (H_dev && e == hipSuccess) e = hamiltonian<T>(g, c, U, P, H_dev + 1, w, s);
+    return hip_status(e);
+  }
+  // The first force pass sees U at the start and the last one U at the end: their
+  // fused action partials give S for H, with the kinetic energy of P taken before the
+  // first kick and after the last.
+  auto finish_h = [&](double* out) {
+    return timed("finish", s, [&] {
+      return sym::launch_finish_hamiltonian(w.act, force_tiles(g), force_kind(), w.kin, sym::link_tiles(g), g, c,
+                                            out, s);
+    });
+  };
+  double* act = H_dev ? w.act : nullptr;
+  if (H_dev) e = timed("kinetic", s, [&] { return sym::launch_kinetic<T>(g, P, w.kin, s); });
+  if (e == hipSuccess) e = force_into<T>(g, U, P, 0.5 * dt, act, c, ForceOut::Kick, w, s);
+  if (H_dev && e == hipSuccess) e = finish_h(H_dev);
   for (int it = 0; it < nsteps && e == hipSuccess; ++it) {
     e = timed("drift", s, [&] { return sym::launch_drift<T>(g, U, P, dt, s); });
     if (e == hipSuccess) {
-      const double kick = (it + 1 == nsteps) ? 0.5 * dt : dt;
-      e = force_into<T>(g, U, P, kick, nullptr, c, ForceOut::Kick, w, s);
+      const bool last = it + 1 == nsteps;
+      e = force_into<T>(g, U, P, last ? 0.5 * dt : dt, last ? act : nullptr, c, ForceOut::Kick, w, s);
     }
   }
-  if (H_dev && e == hipSuccess) e = hamiltonian<T>(g, c, U, P, H_dev + 1, w, s);
+  if (H_dev && e == hipSuccess) e = timed("kinetic", s, [&] { return sym::launch_kinetic<T>(g, P, w.kin, s); });
+  if (H_dev && e == hipSuccess) e = finish_h(H_dev + 1);
   return hip_status(e);
 }
 
