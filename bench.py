@@ -411,6 +411,36 @@ def copy_calibration(torch, nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def measured_peaks(sym, torch):
+    """Device rates the roofline fractions can be read against: vector FMA throughput
+    (sym_fma_probe, this build's non-packed FP32 and FP64 FMAs) and HBM bandwidth of a
+    plain 2 GiB device copy (read + write) and fill (write), best of 5."""
+    res = {"fp32_fma_tflops": sym.fma_rate(torch.float32), "fp64_fma_tflops": sym.fma_rate(torch.float64)}
+    n = 1 << 29  # 2 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            t = ms if t is None else min(t, ms)
+        return t * 1e-3
+
+    res["hbm_copy_tbs"] = 2 * 4 * n / best(lambda: b.copy_(a)) / 1e12
+    res["hbm_write_tbs"] = 4 * n / best(lambda: b.fill_(2.0)) / 1e12
+    del a, b
+    log(f"  measured peaks: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +455,7 @@ def main():
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd timing")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the device peak measurements")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -444,7 +475,7 @@ def main():
 
     if args.only_f32:
         args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = args.no_fat = True
-        args.no_wilson = args.no_autograd = True
+        args.no_wilson = args.no_autograd = args.no_peaks = True
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]
@@ -572,6 +603,13 @@ def main():
         log("timing the Wilson-clover force")
         out["wilson_clover_force"] = bench_wilson(sym, torch, U_np, L, args.steps, args.warmup,
                                                   with_fp64=not args.no_fp64, with_cpu=not args.no_cpu_baseline)
+
+    if not args.no_peaks:
+        log("measuring device peaks")
+        out["measured_peaks"] = measured_peaks(sym, torch)
+        mp = out["measured_peaks"]["fp32_fma_tflops"]
+        out["roofline"]["measured_peak"] = mp
+        out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / mp
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")

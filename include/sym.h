@@ -258,6 +258,16 @@ const char* sym_strerror(int status);
 int sym_profile_enable(int on);
 int sym_profile_collect(int max_kinds, char* names, double* total_ms, int32_t* launches);
 
+/*
+ * Vector FMA-rate probe, for quoting roofline fractions against a measured peak: one
+ * launch of 4096 workgroups x 256 threads, each thread running 8 independent chains of
+ * `iters` fused multiply-adds in precision prec with no memory traffic in the loop
+ * (2 x 8 x iters x 4096 x 256 flop). out: device buffer of 4096 x 256 elements of prec
+ * (written, one value per thread). iters in [1, 2^20], else SYM_EINVAL. The caller
+ * times the call (e.g. with events on `stream`).
+ */
+int sym_fma_probe(int prec, int32_t iters, void* out, sym_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

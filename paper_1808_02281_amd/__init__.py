@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     fat_links,
     fat_workspace,
     field_shape,
+    fma_rate,
     force,
     md_leapfrog,
     new_fat_workspace,

@@ -40,6 +40,7 @@ EXPORTS = (
     "sym_wilson_force",
     "sym_pack_spinor",
     "sym_unpack_spinor",
+    "sym_fma_probe",
 )
 FAT_MODES = {"grad": 0, "force": 1}
 FAT_REUSE_LINKS = 2
@@ -93,6 +94,8 @@ def lib():
     L.sym_profile_enable.restype = ctypes.c_int
     L.sym_profile_collect.argtypes = [ctypes.c_int, ctypes.c_char_p, dp, i32p]
     L.sym_profile_collect.restype = ctypes.c_int
+    L.sym_fma_probe.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.sym_fma_probe.restype = ctypes.c_int
     L.sym_batch_workspace_bytes.argtypes = [ctypes.c_int, i32p, ctypes.c_int]
     L.sym_batch_workspace_bytes.restype = ctypes.c_size_t
     L.sym_force_batch.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp,

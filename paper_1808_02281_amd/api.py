@@ -427,3 +427,26 @@ def wilson_force(U, X, Y, L, kappa, csw, out=None):
                                                                _ptr(X), _ptr(Y), _ptr(G), _ptr(ws), ws.numel(),
                                                                _stream(U.device)))
     return G
+
+
+def fma_rate(dtype=torch.float32, iters=8192, device="cuda:0", reps=5):
+    """Measured vector FMA throughput in TFLOP/s (sym_fma_probe; best of ``reps``)."""
+    prec = prec_of(dtype)
+    dev = torch.device(device)
+    out = torch.empty(4096 * 256, dtype=dtype, device=dev)
+    call = lambda: _lib.check("sym_fma_probe", _lib.lib().sym_fma_probe(prec, int(iters), _ptr(out), _stream(dev)))
+    call()
+    torch.cuda.synchronize(dev)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    if not torch.isfinite(out).all():
+        raise RuntimeError("FMA probe produced non-finite values")
+    return 2.0 * 8 * iters * 4096 * 256 / (best * 1e-3) / 1e12
+

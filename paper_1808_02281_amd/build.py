@@ -36,6 +36,7 @@ UNITS = [
     ("fat.hip", ["-DSYM_ONLY_F32"], "fat_f32.o"),
     ("fat.hip", ["-DSYM_ONLY_F64"], "fat_f64.o"),
     ("wilson.hip", [], "wilson.o"),
+    ("probe.hip", [], "probe.o"),
 ]
 
 

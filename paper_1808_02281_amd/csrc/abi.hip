@@ -616,6 +616,16 @@ int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U
                          : do_fat_links<float>(g, cf, U, V, W, fat_carve<float>(ws, g, prec), s);
 }
 
+int sym_fma_probe(int prec, int32_t iters, void* out, sym_stream_t stream) {
+  int rc;
+  if ((rc = check_prec(prec)) || (rc = check_ptr(out))) return rc;
+  if (iters < 1 || iters > (1 << 20)) return SYM_EINVAL;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e = prec == SYM_F64 ? sym::launch_fma_probe<double>(static_cast<double*>(out), iters, s)
+                                       : sym::launch_fma_probe<float>(static_cast<float*>(out), iters, s);
+  return hip_status(e);
+}
+
 int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U, const void* GV, const void* GW,
                   void* out, int mode, void* ws, size_t ws_bytes, sym_stream_t stream) {
   Geom g;

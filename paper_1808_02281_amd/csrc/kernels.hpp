@@ -125,4 +125,10 @@ hipError_t launch_wilson_force(const Geom& g, const T* U, const T* X, const T* Y
 template <typename T>
 hipError_t launch_spinor_layout(const Geom& g, const T* src, T* dst, bool pack, hipStream_t s);
 
+// FMA-rate probe (probe.hip): kProbeBlocks workgroups of 256 threads, each thread 8
+// independent chains of `iters` FMAs, one value per thread written to out.
+constexpr int kProbeBlocks = 4096;
+template <typename T>
+hipError_t launch_fma_probe(T* out, int iters, hipStream_t s);
+
 }  // namespace sym

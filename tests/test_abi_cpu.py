@@ -159,3 +159,11 @@ def test_wilson_validation(L_):
     assert w(ok, 1, 0.12, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, 16, None) == -3
     assert L_.sym_pack_spinor(_dims(4, 4, 4, 3), 1, FAKE, FAKE, None) == -1
     assert L_.sym_unpack_spinor(ok, 1, None, FAKE, None) == -2
+
+
+def test_fma_probe_validation(L_):
+    assert L_.sym_fma_probe(3, 16, FAKE, None) == -1
+    assert L_.sym_fma_probe(1, 0, FAKE, None) == -1
+    assert L_.sym_fma_probe(1, (1 << 20) + 1, FAKE, None) == -1
+    assert L_.sym_fma_probe(2, 16, None, None) == -2
+
