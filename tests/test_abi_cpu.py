@@ -167,3 +167,28 @@ def test_fma_probe_validation(L_):
     assert L_.sym_fma_probe(1, (1 << 20) + 1, FAKE, None) == -1
     assert L_.sym_fma_probe(2, 16, None, None) == -2
 
+
+def test_batch_validation(L_):
+    """Every call below is rejected before anything is launched."""
+    two = (ctypes.c_int32 * 8)(4, 4, 4, 4, 6, 6, 6, 8)
+    bad = (ctypes.c_int32 * 8)(4, 4, 4, 4, 6, 6, 5, 8)
+    ptrs = (ctypes.c_void_p * 2)(0x100000, 0x200000)
+    holes = (ctypes.c_void_p * 2)(0x100000, None)
+    wb = L_.sym_batch_workspace_bytes
+    assert wb(2, two, 1) > 0 and wb(2, two, 2) > wb(2, two, 1)
+    assert wb(0, two, 1) == 0 and wb(2, bad, 1) == 0 and wb(2, None, 1) == 0 and wb(2, two, 3) == 0
+    fb = L_.sym_force_batch
+    assert fb(0, two, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
+    assert fb(2, bad, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
+    assert fb(2, None, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -2
+    assert fb(2, two, -1.0, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
+    assert fb(2, two, 0.8677, 3.0, 1, holes, ptrs, None, FAKE, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, None, None, FAKE, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, MISALIGNED, FAKE, HUGE, None) == -1
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, None, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, 64, None) == -3
+    at = L_.sym_batch_autotune
+    assert at(0, two, 0.8677, 3.0, 1, ptrs, ptrs, FAKE, HUGE, None, None, None) == -1
+    assert at(2, two, 0.8677, 3.0, 2, holes, ptrs, FAKE, HUGE, None, None, None) == -2
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, ptrs, FAKE, 64, None, None, None) == -3
+
