@@ -525,7 +525,8 @@ def main():
         "kernel_ms": t_dom * 1e3,
     }
     if traffic:
-        roofline["hbm_frac_measured"] = traffic / t_dom / PEAK_HBM
+        # FETCH_SIZE/WRITE_SIZE count bytes leaving the L2s, Infinity Cache hits included
+        roofline["l2_egress_frac_of_hbm_peak"] = traffic / t_dom / PEAK_HBM
     paper_equiv = FLOP_PAPER * value
     out = {
         "metric": METRIC,
