@@ -29,26 +29,25 @@ __global__ __launch_bounds__(kBlock) void fat_fk2_kernel(Geom g, const T* __rest
   if (cb >= g.Vh) return;
   Ctx<T> c;
   fat::make_ctx(g, U, lt.mu, lt.p, cb, c);
-  if constexpr (sizeof(T) == 4) {
-    su3<T> acc[3];
-    const su3<T> u = c.template u<0, 0, 0, 0, 0>();
+  // transport direction outermost (two_out), both precisions; FP64 holds the three
+  // accumulators in VGPRs and AGPRs at one wave per SIMD (6.05 -> 4.71 ms at 32^3 x 64
+  // against one M at a time)
+  su3<T> acc[3];
+  const su3<T> u = c.template u<0, 0, 0, 0, 0>();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      acc[k] = u;
-      fat::scale(acc[k], T(cf.c[1]));
-    }
-    SYM_FAT_FENCE();
-    fat::two_out<1, false>(acc, c, static_cast<const T*>(w.inner));
-    fat::launder(c);
-    SYM_FAT_FENCE();
-    fat::store_m<1>(acc[0], c, w, T(cf.c[4]), cb);
-    SYM_FAT_FENCE();
-    fat::store_m<2>(acc[1], c, w, T(cf.c[4]), cb);
-    SYM_FAT_FENCE();
-    fat::store_m<3>(acc[2], c, w, T(cf.c[4]), cb);
-  } else {
-    fat::fk2_step<1>(c, w, cf, cb);
+  for (int k = 0; k < 3; ++k) {
+    acc[k] = u;
+    fat::scale(acc[k], T(cf.c[1]));
   }
+  SYM_FAT_FENCE();
+  fat::two_out<1, false>(acc, c, static_cast<const T*>(w.inner));
+  fat::launder(c);
+  SYM_FAT_FENCE();
+  fat::store_m<1>(acc[0], c, w, T(cf.c[4]), cb);
+  SYM_FAT_FENCE();
+  fat::store_m<2>(acc[1], c, w, T(cf.c[4]), cb);
+  SYM_FAT_FENCE();
+  fat::store_m<3>(acc[2], c, w, T(cf.c[4]), cb);
 }
 
 template <typename T>
@@ -97,24 +96,21 @@ __global__ __launch_bounds__(kBlock) void fat_bk2_kernel(Geom g, const T* __rest
   fat::scale(dsum, T(cf.c[0]));
   for (int k = 0; k < 3; ++k) axpy(dsum, T(cf.c[1]), c.template f<0, 0, 0, 0, 0>(w.gmid, 3, k));
   SYM_FAT_FENCE();
-  if constexpr (sizeof(T) == 4) {
-    su3<T> gi[3];
+  // transport direction outermost, both precisions (FP64: 6.78 -> 5.50 ms at 32^3 x 64)
+  su3<T> gi[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) set_zero(gi[k]);
-    fat::two_out<1, true>(gi, c, static_cast<const T*>(w.gmid));
-    fat::launder(c);
-    const T c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]);
-    SYM_FAT_FENCE();
-    fat::store_gt<1>(gi[0], c, GV, w, c7, cL, cb);
-    SYM_FAT_FENCE();
-    fat::store_gt<2>(gi[1], c, GV, w, c7, cL, cb);
-    SYM_FAT_FENCE();
-    fat::store_gt<3>(gi[2], c, GV, w, c7, cL, cb);
+  for (int k = 0; k < 3; ++k) set_zero(gi[k]);
+  fat::two_out<1, true>(gi, c, static_cast<const T*>(w.gmid));
+  fat::launder(c);
+  const T c5 = T(cf.c[2]), c7 = T(cf.c[3]), cL = T(cf.c[4]);
+  SYM_FAT_FENCE();
+  fat::store_gt<1>(gi[0], c, GV, w, c7, cL, cb);
+  SYM_FAT_FENCE();
+  fat::store_gt<2>(gi[1], c, GV, w, c7, cL, cb);
+  SYM_FAT_FENCE();
+  fat::store_gt<3>(gi[2], c, GV, w, c7, cL, cb);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) axpy(dsum, c5, gi[m]);
-  } else {
-    fat::bk2_step<1>(c, GV, w, cf, dsum, cb);
-  }
+  for (int m = 0; m < 3; ++m) axpy(dsum, c5, gi[m]);
   fat::store_slot(w.D, 1, 0, lt.mu, lt.p, g.Vh, cb, dsum);
 }
 

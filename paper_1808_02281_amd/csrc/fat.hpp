@@ -333,41 +333,6 @@ __device__ __forceinline__ void store_gt(const su3<T>& gi, const Ctx<T>& c0, con
   store_slot(w.gT1, 6, 2 * (M - 1) + 1, c.ax[0], c.p, c.Vh, cb, t);
 }
 
-// FK2: midc_K = c3 U_mu + sum_{J != K} sum_s Sts_{ax[J]}(inner[M]), M the third axis;
-// stores M[K, s] = midc_K + cL T1[K, s]
-template <int K, int J, typename T>
-__device__ __forceinline__ void fk2_inner(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
-  if constexpr (J <= 3) {
-    if constexpr (J != K) {
-      Ctx<T> c = c0;
-      launder(c);
-      constexpr int M = 6 - K - J;
-      const auto A = one(static_cast<const T*>(w.inner), 3, M - 1);
-      st_acc<J, 1>(acc, c, A);
-      SYM_FAT_FENCE();
-      st_acc<J, -1>(acc, c, A);
-      SYM_FAT_FENCE();
-    }
-    fk2_inner<K, J + 1>(acc, c0, w);
-  }
-}
-
-template <int K, typename T>
-__device__ __forceinline__ void fk2_step(const Ctx<T>& c0, const Fields<T>& w, const FatCoeffs& cf, int cb) {
-  if constexpr (K <= 3) {
-    Ctx<T> c = c0;
-    launder(c);
-    su3<T> acc = c.template u<0, 0, 0, 0, 0>();
-    scale(acc, T(cf.c[1]));
-    fk2_inner<K, 1>(acc, c, w);
-    const T cL = T(cf.c[4]);
-    SYM_FAT_FENCE();
-    store_m<K>(acc, c, w, cL, cb);
-    SYM_FAT_FENCE();
-    fk2_step<K + 1>(c0, w, cf, cb);
-  }
-}
-
 // FK3: V_mu = c1 U_mu + sum_{K,s} Sts_{ax[K]}(M[K, s])
 template <int K, typename T>
 __device__ __forceinline__ void fk3_step(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
@@ -405,43 +370,11 @@ __device__ __forceinline__ void bk3_step(const Ctx<T>& c0, const T* GV, const Fi
   }
 }
 
-// BK2: g_inner_M = sum_{(K,J): {K,J,M} = {1,2,3}} sum_s Sts_{ax[J]}(gmid_K); stores
-// gT1[M, s] = c7 g_inner_M + cL gM[M, s]; returns c5 g_inner_M added into dsum
-template <int M, int K, typename T>
-__device__ __forceinline__ void bk2_inner(su3<T>& acc, const Ctx<T>& c0, const Fields<T>& w) {
-  if constexpr (K <= 3) {
-    if constexpr (K != M) {
-      constexpr int J = 6 - K - M;
-      Ctx<T> c = c0;
-      launder(c);
-      const auto G = one(static_cast<const T*>(w.gmid), 3, K - 1);
-      st_acc<J, 1>(acc, c, G);
-      SYM_FAT_FENCE();
-      st_acc<J, -1>(acc, c, G);
-      SYM_FAT_FENCE();
-    }
-    bk2_inner<M, K + 1>(acc, c0, w);
-  }
-}
-
-template <int M, typename T>
-__device__ __forceinline__ void bk2_step(const Ctx<T>& c0, const T* GV, const Fields<T>& w, const FatCoeffs& cf,
-                                         su3<T>& dsum, int cb) {
-  if constexpr (M <= 3) {
-    Ctx<T> c = c0;
-    launder(c);
-    su3<T> gi;
-    set_zero(gi);
-    bk2_inner<M, 1>(gi, c, w);
-    SYM_FAT_FENCE();
-    store_gt<M>(gi, c, GV, w, T(cf.c[3]), T(cf.c[4]), cb);
-    axpy(dsum, T(cf.c[2]), gi);
-    SYM_FAT_FENCE();
-    bk2_step<M + 1>(c0, GV, w, cf, dsum, cb);
-  }
-}
-
-// FK2 and BK2 with the transport direction J outermost (FP32): each transport along
+// FK2: midc_K = c3 U_mu + sum_{J != K} sum_s Sts_{ax[J]}(inner[M]), M the third axis,
+// stores M[K, s] = midc_K + cL T1[K, s] (store_m). BK2: g_inner_M = sum over (K, J)
+// with {K, J, M} = {1, 2, 3} of sum_s Sts_{ax[J]}(gmid_K), stores gT1 (store_gt) and
+// adds c5 g_inner_M into D.
+// Both with the transport direction J outermost: each transport along
 // ax[J] serves two outputs, so its four links (U_{x,J}, U_{x+mu,J}, U_{x-J,J},
 // U_{x-J+mu,J}) are loaded once for both; the three accumulators stay in registers.
 // acc[K-1] += sum_s Sts_{ax[J]}(F[slot(K)]) for the two K != J, where (K, J, M) is a
@@ -507,8 +440,10 @@ __device__ __forceinline__ void gk_pull(su3<T>& acc, const Ctx<T>& c0, const Fie
 // above. Eight transports per mu: (GV, M[nu,s]) from V, (gmid_k, inner_m) from midc for
 // the two k other than nu, (gT1[nu,s], U_mu) from T1. The two links are loaded once per
 // mu; in FP32 the four matrices of the next transport are requested before the current
-// one is multiplied out (FP64 has no registers for two transports; loading the links once
-// took its gather from 19.5 to 14.4 ms at 32^3 x 64, and FP32 went from 8.5 to 7.0 ms).
+// one is multiplied out (FP64 keeps one transport at a time: with the look-ahead its
+// operands overflow VGPRs and AGPRs, spill 48 bytes and measured 14.8 against 14.5 ms;
+// loading the links once took its gather from 19.5 to 14.4 ms at 32^3 x 64, and FP32
+// went from 8.5 to 7.0 ms).
 template <typename T>
 struct Dep {
   su3<T> x0, x1, y0, y1;
