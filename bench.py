@@ -7,7 +7,8 @@ action reduction), on fields resident in HBM in the even-odd SoA layout. The
 headline is FP32 link products with FP64 action; the FP64 form is timed beside it.
 
 Prints one JSON line (metric, value = link-forces/s, roofline of the dominant kernel,
-CPU-oracle baseline, FP64 comparison, leapfrog step timing).
+CPU-oracle baseline, errors of the FP32 and FP64 forces and actions against the FP64
+oracle on every link, FP64 timing, leapfrog step timing and the other rows).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
   python bench.py --copy-calibration      # plain copy kernel for rocprof byte counters
@@ -57,7 +58,8 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}   # MI355X vector peaks (FP32 counts pa
 PEAK_F32_NONPACKED = 78.6e12               # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_HBM = 8.0e12
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_factored_f32_32x32x32x64_traffic.json")
+TRAFFIC_FILES = {p: os.path.join(ROOT, "profiles", f"force_factored_{p}_32x32x32x64_traffic.json")
+                 for p in ("f32", "f64")}
 KERNEL_SOURCES = ["force_factored.hip", "factored.hpp", "su3.hpp", "lattice.hpp", "kernels.hpp"]
 
 
@@ -69,11 +71,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(prec):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3 counters, or
     None when absent or taken on a different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[prec]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -87,15 +89,14 @@ def log(msg):
 
 
 def time_force(sym, torch, U, L, u0, beta, steps, warmup):
+    """Time `steps` force calls with the fused action (no profiling hooks in the timed
+    loop), then the same number again with per-kernel HIP events for the kernel split."""
     F = torch.empty_like(U)
     for _ in range(warmup):
         sym.force(U, L, u0, beta, with_action=True, out=F)
     torch.cuda.synchronize()
-    sym.profile_enable(True)
-    sym.profile_collect()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
     S = None
@@ -104,10 +105,32 @@ def time_force(sym, torch, U, L, u0, beta, steps, warmup):
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / steps
+    sym.profile_enable(True)
+    sym.profile_collect()
+    for _ in range(steps):
+        sym.force(U, L, u0, beta, with_action=True, out=F)
+    torch.cuda.synchronize()
     kernels = sym.profile_collect()
     sym.profile_enable(False)
-    ms = start.elapsed_time(end) / steps
-    return ms, wall, kernels, F, float(S[0].item())
+    return ms, wall, kernels, F, S.cpu().numpy()
+
+
+def force_error_report(G, G_ref, S, S_ref):
+    """Errors of a GPU force and action against the oracle's, in the norms the tests
+    gate: max over links of the Frobenius error / max over links of the reference norm,
+    the RMS ratio, the worst per-link relative error and where it is, and |S - S_ref|/|S_ref|."""
+    import numpy as np
+
+    d = np.sqrt(np.sum(np.abs(G - G_ref) ** 2, axis=(-2, -1))).reshape(-1)
+    r = np.sqrt(np.sum(np.abs(G_ref) ** 2, axis=(-2, -1))).reshape(-1)
+    rel = d / np.maximum(r, 1e-300)
+    k = int(np.argmax(rel))
+    return {"force_max_rel": float(d.max() / r.max()),
+            "force_rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(r * r))),
+            "force_worst_link_rel": float(rel[k]),
+            "worst_link": {"site": k // 4, "mu": k % 4},
+            "action_rel": float(abs(S - S_ref) / abs(S_ref))}
 
 
 def bench_batch(sym, torch, gaugegen, u0, beta, reps=20):
@@ -373,32 +396,60 @@ def bench_autograd(sym, torch, gaugegen, u0, beta, steps, warmup):
     return out
 
 
-def cpu_baseline(U_np, L, u0, beta, budget_s=12.0):
-    """The FP64 oracle's force on a random sample of links of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(U_np, L, u0, beta, one_thread_budget_s=8.0):
+    """The FP64 oracle's force on every link of the workload with OpenMP on all host
+    threads (the timed value; its forces and action are kept for the error report), and
+    on a random sample of links at one thread."""
     import numpy as np
 
     import oracle
 
     c, _ = oracle.coeffs(u0)
     V = int(np.prod(L))
+    threads = oracle.set_num_threads(os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    G_ref = oracle.force(U_np, L, c, beta)
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    S_ref = oracle.action(U_np, L, c, beta)[0]
+    dt_action = time.perf_counter() - t1
+    log(f"  oracle force on all {4 * V} links: {dt:.1f} s on {threads} threads; action {dt_action:.1f} s")
+    one = oracle.set_num_threads(1)
     rng = np.random.default_rng(99)
-    n = 4096
+    n = 2048
     while True:
         sites = rng.integers(0, V, n)
         mus = rng.integers(0, 4, n).astype(np.int32)
-        t0 = time.perf_counter()
+        t2 = time.perf_counter()
         oracle.force_links(U_np, L, c, beta, sites, mus)
-        dt = time.perf_counter() - t0
-        if dt >= budget_s / 4 or n >= 4 * V:
+        dt1 = time.perf_counter() - t2
+        if dt1 >= one_thread_budget_s / 4:
             break
-        n = min(4 * V, int(n * max(2.0, budget_s / max(dt, 1e-3) * 0.9)))
-    return {
-        "value": n / dt,
+        n = int(n * max(2.0, one_thread_budget_s / max(dt1, 1e-3) * 0.9))
+    oracle.set_num_threads(threads)
+    base = {
+        "value": 4 * V / dt,
         "unit": "link-forces/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{n} random links of the 32^3x64 workload, FP64, C oracle with OpenMP ({dt:.1f} s)",
+        "sample": f"every link ({4 * V}) of the 32^3x64 workload, FP64, C oracle with OpenMP ({dt:.1f} s)",
+        "value_1_thread": n / dt1,
+        "sample_1_thread": f"{n} random links of the same workload, one thread ({dt1:.1f} s)",
+        "host_threads": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
+    return base, G_ref, S_ref
 
 
 def copy_calibration(torch, nbytes=1 << 30, reps=5):
@@ -411,11 +462,48 @@ def copy_calibration(torch, nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def fma_rate(torch, dtype, iters=8192, reps=5):
+    """Measured vector FMA throughput in TFLOP/s: the probe kernel of libsymprobe.so (a
+    benchmark helper built beside libsym.so, not part of its ABI), best of ``reps``."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_1808_02281_amd", "libsymprobe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP libraries first (__graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    lib.probe_fma.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.probe_fma.restype = ctypes.c_int
+    prec = {torch.float32: 1, torch.float64: 2}[dtype]
+    dev = torch.device("cuda:0")
+    out = torch.empty(4096 * 256, dtype=dtype, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+    def call():
+        rc = lib.probe_fma(prec, int(iters), ctypes.c_void_p(out.data_ptr()), stream)
+        if rc != 0:
+            raise RuntimeError(f"probe_fma failed with status {rc}")
+
+    call()
+    torch.cuda.synchronize(dev)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    if not torch.isfinite(out).all():
+        raise RuntimeError("FMA probe produced non-finite values")
+    return 2.0 * 8 * iters * 4096 * 256 / (best * 1e-3) / 1e12
+
+
 def measured_peaks(sym, torch):
     """Device rates the roofline fractions can be read against: vector FMA throughput
-    (sym_fma_probe, this build's non-packed FP32 and FP64 FMAs) and HBM bandwidth of a
+    (the probe kernel, this build's non-packed FP32 and FP64 FMAs) and HBM bandwidth of a
     plain 2 GiB device copy (read + write) and fill (write), best of 5."""
-    res = {"fp32_fma_tflops": sym.fma_rate(torch.float32), "fp64_fma_tflops": sym.fma_rate(torch.float64)}
+    res = {"fp32_fma_tflops": fma_rate(torch, torch.float32), "fp64_fma_tflops": fma_rate(torch, torch.float64)}
     n = 1 << 29  # 2 GiB of float32
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
@@ -503,30 +591,34 @@ def main():
         tot, n = kernels.get(name, (0.0, 0))
         return tot / n if n else None
 
-    dom = "force_factored" if "force_factored" in k32 else "force_direct"
-    t_dom = kernel_avg(k32, dom) * 1e-3
-    flop_dom = FLOP_FACTORED if dom == "force_factored" else FLOP_DIRECT
-    bytes_dom = (BYTES_FACTORED if dom == "force_factored" else BYTES_DIRECT)(4)
-    alu = flop_dom * links / t_dom
-    hbm = bytes_dom * links / t_dom
-    traffic = measured_traffic() if dom == "force_factored" else None
-    roofline = {
-        "kernel": dom,
-        "bound": "alu",
-        "achieved": alu / 1e12,
-        "peak": PEAK["f32"] / 1e12,
-        "unit": "TFLOP/s",
-        "frac": alu / PEAK["f32"],
-        "traffic": traffic,
-        "flop_per_link": flop_dom,
-        "frac_of_nonpacked_fp32_peak": alu / PEAK_F32_NONPACKED,
-        "hbm_min_bytes_per_link": bytes_dom,
-        "hbm_frac_at_min_bytes": hbm / PEAK_HBM,
-        "kernel_ms": t_dom * 1e3,
-    }
-    if traffic:
-        # FETCH_SIZE/WRITE_SIZE count bytes leaving the L2s, Infinity Cache hits included
-        roofline["l2_egress_frac_of_hbm_peak"] = traffic / t_dom / PEAK_HBM
+    def roofline_of(kernels, prec):
+        dom = "force_factored" if "force_factored" in kernels else "force_direct"
+        t_dom = kernel_avg(kernels, dom) * 1e-3
+        flop_dom = FLOP_FACTORED if dom == "force_factored" else FLOP_DIRECT
+        bytes_dom = (BYTES_FACTORED if dom == "force_factored" else BYTES_DIRECT)(4 if prec == "f32" else 8)
+        alu = flop_dom * links / t_dom
+        hbm = bytes_dom * links / t_dom
+        r = {
+            "kernel": dom,
+            "bound": "alu",
+            "achieved": alu / 1e12,
+            "peak": PEAK[prec] / 1e12,
+            "unit": "TFLOP/s",
+            "frac": alu / PEAK[prec],
+            "traffic": measured_traffic(prec) if dom == "force_factored" else None,
+            "flop_per_link": flop_dom,
+            "hbm_min_bytes_per_link": bytes_dom,
+            "hbm_frac_at_min_bytes": hbm / PEAK_HBM,
+            "kernel_ms": t_dom * 1e3,
+        }
+        if prec == "f32":
+            r["frac_of_nonpacked_fp32_peak"] = alu / PEAK_F32_NONPACKED
+        if r["traffic"]:
+            # FETCH_SIZE/WRITE_SIZE count bytes leaving the L2s, Infinity Cache hits included
+            r["l2_egress_frac_of_hbm_peak"] = r["traffic"] / t_dom / PEAK_HBM
+        return dom, r
+
+    dom, roofline = roofline_of(k32, "f32")
     paper_equiv = FLOP_PAPER * value
     out = {
         "metric": METRIC,
@@ -548,21 +640,24 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in k32.items()},
         "paper_equivalent": {"flop_per_link": FLOP_PAPER, "tflops": paper_equiv / 1e12,
                              "frac_of_fp32_peak": paper_equiv / PEAK["f32"]},
-        "action_f32": S32,
+        "action_f32": S32.tolist(),
         "wall_s": wall32,
     }
+    # the forces leave the GPU for the comparison with the oracle at the end
+    G32_host = sym.unpack(F32, L).cpu().numpy() if not args.no_cpu_baseline else None
+    G64_host = None
+    del F32
 
     if not args.no_fp64:
         log("timing FP64 force")
         ms64, _, k64, F64, S64 = time_force(sym, torch, U64, L, u0, beta, args.steps, args.warmup)
-        d = (F32.to(torch.float64) - F64).reshape(4, 2, 9, -1, 2)
-        dn = torch.sqrt((d * d).sum(dim=(2, 4))).max().item()
-        rn = torch.sqrt((F64.reshape(4, 2, 9, -1, 2) ** 2).sum(dim=(2, 4))).max().item()
         out["fp64"] = {"value": links / (ms64 * 1e-3), "ms_per_step": ms64,
                        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in k64.items()},
-                       "action": S64}
+                       "roofline": roofline_of(k64, "f64")[1],
+                       "action": S64.tolist()}
         out["fp32_speedup_over_fp64"] = ms64 / ms32
-        out["fp32_vs_fp64"] = {"force_max_rel": dn / rn, "action_rel": abs(S32 - S64) / abs(S64)}
+        if not args.no_cpu_baseline:
+            G64_host = sym.unpack(F64, L).cpu().numpy()
         del F64
         log(f"  {ms64:.3f} ms/step")
 
@@ -611,10 +706,25 @@ def main():
         mp = out["measured_peaks"]["fp32_fma_tflops"]
         out["roofline"]["measured_peak"] = mp
         out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / mp
+        if "fp64" in out:
+            mp64 = out["measured_peaks"]["fp64_fma_tflops"]
+            out["fp64"]["roofline"]["measured_peak"] = mp64
+            out["fp64"]["roofline"]["frac_of_measured_peak"] = out["fp64"]["roofline"]["achieved"] / mp64
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(U_np, L, u0, beta)
+        out["cpu_baseline"], G_ref, S_ref = cpu_baseline(U_np, L, u0, beta)
+        # errors of the timed results against the FP64 oracle on the same (unrounded)
+        # links: end to end for FP32, whose kernel error on the rounded links is gated
+        # at 1e-5 by the tests
+        log("comparing with the oracle")
+        err = {"reference": "FP64 oracle, every link of the workload, unrounded FP64 links",
+               "f32": force_error_report(G32_host.astype(np.complex128), G_ref, S32[0], S_ref)}
+        if G64_host is not None:
+            err["f64"] = force_error_report(G64_host, G_ref, S64[0], S_ref)
+        err["tolerance"] = {"f32": 1e-5, "f64": 1e-12}
+        out["error_vs_oracle"] = err
+        log(f"  {err}")
     print(json.dumps(out), flush=True)
 
 

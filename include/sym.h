@@ -31,7 +31,10 @@
  *   All work is enqueued on `stream` (a hipStream_t; NULL = default stream) and the
  *   calls return without synchronising; results such as S_dev are device doubles.
  *   Arguments are validated on the host before anything is launched; a negative
- *   sym_status is returned and nothing is enqueued. A failed launch returns SYM_EHIP;
+ *   sym_status is returned and nothing is enqueued. The device regions of one call
+ *   (fields it writes, fields it reads, the scalar outputs and the part of ws it uses)
+ *   must not overlap, since kernels read neighbouring links while writing; overlapping
+ *   regions give SYM_EINVAL (fields that are only read may coincide). A failed launch returns SYM_EHIP;
  *   faults inside kernels surface at the caller's next synchronisation. Nothing throws
  *   or aborts across this interface. Calls on different streams with different
  *   workspaces may run concurrently.
@@ -88,9 +91,13 @@ int sym_action(const int32_t L[4], double u0, double beta, int prec, const void*
  * sum of the 48 staples of the link and TA of eq. 18_6_6_11. G is traceless and
  * antihermitian; the paper's Hermitian force -sum_i T_i dS/domega^i is iG, and
  * dS/domega^a = -2i tr(T_a G) for U -> exp(i omega.T) U. U: link field (read);
- * F: output, same layout. S_dev: NULL, or 4 device doubles that receive the action as
- * in sym_action, computed from the same staple sums (each loop of class X is seen once
- * from each of its L_X = 4, 6, 6 links).
+ * F: output, same layout, disjoint from U (else SYM_EINVAL). S_dev: NULL, or 4 device
+ * doubles that receive the action as in sym_action, computed from the same staple sums
+ * (each loop of class X is seen once from each of its L_X = 4, 6, 6 links); when the
+ * factored algorithm runs with c_cube = 0 (u0 = 1, or an override) those sums do not
+ * separate W_C, and the action kernel of sym_action fills S_dev after the force pass.
+ * The factored algorithm (the default) requires special-unitary links; see
+ * sym_set_force_algorithm and sym_check_links.
  */
 int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* U, void* F, double* S_dev, void* ws,
               size_t ws_bytes, sym_stream_t stream);
@@ -111,8 +118,13 @@ int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const 
  * with U-dot = Pi U and Pi-dot = -G (U = exp(i omega.T), dU/domega = iTU; Sec. II):
  * per step Pi -= dt/2 G(U); U <- exp(dt Pi) U; Pi -= dt/2 G(U), consecutive half kicks
  * merged. The exponential and U update are in double. U: links (in/out); P: momenta
- * Pi = i sum_a p_a T_a, antihermitian (in/out). H_dev: NULL or 2 device doubles,
- * {H before, H after}. No reunitarisation.
+ * Pi = i sum_a p_a T_a, antihermitian (in/out), disjoint from U. H_dev: NULL or 2 device
+ * doubles, {H before, H after}. SYM_F64: the updated links are stored as computed
+ * (unitary to double rounding, no reunitarisation). SYM_F32: each updated link is
+ * projected onto SU(3) in double (Gram-Schmidt of the first two rows, third row their
+ * conjugate cross product) before it is rounded to float, so the unitarity defect stays
+ * at float rounding (about 1e-7) however many steps are taken; the projection moves a
+ * link by its defect, far below the FP32 force tolerance.
  */
 int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,
                 double* H_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
@@ -219,6 +231,18 @@ int sym_wilson_force(const int32_t L[4], int prec, double kappa, double csw, con
 int sym_pack_spinor(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack_spinor(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);
 
+/*
+ * Link-field check, the precondition of the factored force (links in SU(3)): writes 3
+ * device doubles to out_dev, {max over links of ||U^dagger U - 1||_F, max over links of
+ * |det U - 1|, number of links with a non-finite element}, computed in double (links with
+ * a non-finite element are left out of the two maxima). U: link field (read). ws: at
+ * least sym_workspace_bytes(L, prec) bytes (per-workgroup partials). Asynchronous like
+ * every other call; a caller that guards a force evaluation compares out_dev[0] and
+ * out_dev[1] with its tolerance (e.g. 1e-5 for FP32 fields) and out_dev[2] with 0.
+ */
+int sym_check_links(const int32_t L[4], int prec, const void* U, double* out_dev, void* ws, size_t ws_bytes,
+                    sym_stream_t stream);
+
 /* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);
@@ -236,9 +260,12 @@ int sym_set_coeffs_override(const double c[3]);
  * matrices; SYM_ALG_FACTORED first forms the 6 plaquette staples of every link in the
  * workspace and builds rectangles and cube loops from them (63 products per link); it
  * reads links and stores staples as two rows and rebuilds the third, which requires
- * the links to be special unitary to working precision (as the paper's link variables are, and as
- * md_leapfrog keeps them). SYM_ALG_AUTO (default) is SYM_ALG_FACTORED.
- * SYM_EINVAL for other values.
+ * the links to be special unitary to working precision, as the paper's link variables
+ * are: for a link off SU(3) by delta (||U^dagger U - 1||), the rebuilt row differs from
+ * the stored one by O(delta), and so does the force. md_leapfrog keeps its links within
+ * float rounding of SU(3) in SYM_F32 and within double rounding in SYM_F64; fields
+ * from elsewhere can be checked with sym_check_links. SYM_ALG_AUTO (default) is
+ * SYM_ALG_FACTORED. SYM_EINVAL for other values.
  */
 int sym_set_force_algorithm(int algorithm);
 
@@ -257,16 +284,6 @@ const char* sym_strerror(int status);
  */
 int sym_profile_enable(int on);
 int sym_profile_collect(int max_kinds, char* names, double* total_ms, int32_t* launches);
-
-/*
- * Vector FMA-rate probe, for quoting roofline fractions against a measured peak: one
- * launch of 4096 workgroups x 256 threads, each thread running 8 independent chains of
- * `iters` fused multiply-adds in precision prec with no memory traffic in the loop
- * (2 x 8 x iters x 4096 x 256 flop). out: device buffer of 4096 x 256 elements of prec
- * (written, one value per thread). iters in [1, 2^20], else SYM_EINVAL. The caller
- * times the call (e.g. with events on `stream`).
- */
-int sym_fma_probe(int prec, int32_t iters, void* out, sym_stream_t stream);
 
 #ifdef __cplusplus
 }

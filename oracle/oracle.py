@@ -79,6 +79,8 @@ def _load():
     lib.orc_wilson_force_links.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -327,6 +329,11 @@ def wilson_force_links(U, X, Y, L, kappa, csw, sites, mus):
 
 def num_threads():
     return _load().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of the oracle's later calls from this thread; returns the count."""
+    return _load().orc_set_num_threads(int(n))
 
 
 def gell_mann():

@@ -456,3 +456,12 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of the calling thread's later parallel regions (timing at a chosen thread
+ * count); n <= 0 leaves the setting unchanged. Returns the resulting count. */
+int orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#endif
+    return orc_num_threads();
+}

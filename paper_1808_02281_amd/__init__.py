@@ -12,12 +12,12 @@ from .api import (  # noqa: F401
     action_grad,
     batch_autotune,
     force_batch,
+    check_links,
     coeffs,
     fat_force,
     fat_links,
     fat_workspace,
     field_shape,
-    fma_rate,
     force,
     md_leapfrog,
     new_fat_workspace,

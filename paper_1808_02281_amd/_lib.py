@@ -40,7 +40,7 @@ EXPORTS = (
     "sym_wilson_force",
     "sym_pack_spinor",
     "sym_unpack_spinor",
-    "sym_fma_probe",
+    "sym_check_links",
 )
 FAT_MODES = {"grad": 0, "force": 1}
 FAT_REUSE_LINKS = 2
@@ -94,8 +94,6 @@ def lib():
     L.sym_profile_enable.restype = ctypes.c_int
     L.sym_profile_collect.argtypes = [ctypes.c_int, ctypes.c_char_p, dp, i32p]
     L.sym_profile_collect.restype = ctypes.c_int
-    L.sym_fma_probe.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    L.sym_fma_probe.restype = ctypes.c_int
     L.sym_batch_workspace_bytes.argtypes = [ctypes.c_int, i32p, ctypes.c_int]
     L.sym_batch_workspace_bytes.restype = ctypes.c_size_t
     L.sym_force_batch.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp,
@@ -119,6 +117,8 @@ def lib():
     L.sym_pack_spinor.restype = ctypes.c_int
     L.sym_unpack_spinor.argtypes = [i32p, ctypes.c_int, vp, vp, vp]
     L.sym_unpack_spinor.restype = ctypes.c_int
+    L.sym_check_links.argtypes = [i32p, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sym_check_links.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -159,6 +159,18 @@ def md_leapfrog(U, P, L, u0, beta, dt, nsteps, with_energy=True):
     return H
 
 
+def check_links(U, L):
+    """{max ||U^+U - 1||_F, max |det U - 1|, non-finite links} of a link field as a float64
+    CUDA tensor of 3 (asynchronous; sym_check_links)."""
+    _check_field("U", U, L)
+    prec = prec_of(U.dtype)
+    ws = workspace(L, prec, U.device)
+    out = torch.empty(3, dtype=torch.float64, device=U.device)
+    _lib.check("sym_check_links", _lib.lib().sym_check_links(_lib.dims(L), prec, _ptr(U), _ptr(out), _ptr(ws),
+                                                             ws.numel(), _stream(U.device)))
+    return out
+
+
 def set_coeffs_override(c):
     """Use loop coefficients c = (c_plaq, c_rect, c_cube) instead of u0's; None restores."""
     if c is None:
@@ -427,26 +439,3 @@ def wilson_force(U, X, Y, L, kappa, csw, out=None):
                                                                _ptr(X), _ptr(Y), _ptr(G), _ptr(ws), ws.numel(),
                                                                _stream(U.device)))
     return G
-
-
-def fma_rate(dtype=torch.float32, iters=8192, device="cuda:0", reps=5):
-    """Measured vector FMA throughput in TFLOP/s (sym_fma_probe; best of ``reps``)."""
-    prec = prec_of(dtype)
-    dev = torch.device(device)
-    out = torch.empty(4096 * 256, dtype=dtype, device=dev)
-    call = lambda: _lib.check("sym_fma_probe", _lib.lib().sym_fma_probe(prec, int(iters), _ptr(out), _stream(dev)))
-    call()
-    torch.cuda.synchronize(dev)
-    best = None
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        call()
-        e1.record()
-        torch.cuda.synchronize(dev)
-        ms = e0.elapsed_time(e1)
-        best = ms if best is None else min(best, ms)
-    if not torch.isfinite(out).all():
-        raise RuntimeError("FMA probe produced non-finite values")
-    return 2.0 * 8 * iters * 4096 * 256 / (best * 1e-3) / 1e12
-

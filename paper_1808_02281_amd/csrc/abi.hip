@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string.h>
@@ -108,6 +109,32 @@ int check_ws(void* ws, size_t ws_bytes, const Geom& g, int prec) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SYM_OK : SYM_EHIP; }
 
+size_t link_field_bytes(const Geom& g, int prec) {
+  const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
+  return (size_t)8 * 9 * 2 * real * (size_t)g.Vh;  // 4 directions x 2 parities x 9 complex
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (a == nullptr || b == nullptr) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+// A device region an entry point reads or writes.
+struct Region {
+  const void* p;
+  size_t n;
+};
+
+// The kernels read neighbouring links (and workspace intermediates) while writing their
+// outputs, so no two regions of one call may overlap (NULL regions are skipped).
+int check_disjoint(std::initializer_list<Region> rs) {
+  for (auto a = rs.begin(); a != rs.end(); ++a)
+    for (auto b = a + 1; b != rs.end(); ++b)
+      if (overlap(a->p, a->n, b->p, b->n)) return SYM_EINVAL;
+  return SYM_OK;
+}
+
 // ------------------------------------------------------------ kernel timing
 struct TimedLaunch {
   const char* name;
@@ -147,6 +174,8 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
   return e;
 }
 
+// The force algorithm is read once per ABI call and passed down, so that the launch and
+// the finish of one call always agree even if another thread switches the algorithm.
 bool use_factored() {
   const int a = g_algorithm.load();
   return a == SYM_ALG_FACTORED || a == SYM_ALG_AUTO;
@@ -155,9 +184,9 @@ bool use_factored() {
 // One force evaluation; G goes to `out` (Store) or is subtracted, times `kick`, from the
 // momenta in `out` (Kick). With act != nullptr the per-workgroup staple partials go there.
 template <typename T>
-hipError_t force_into(const Geom& g, const T* U, T* out, double kick, double* act, const Coeffs& c, ForceOut mode,
-                      const Workspace& w, hipStream_t s) {
-  if (use_factored()) {
+hipError_t force_into(bool factored, const Geom& g, const T* U, T* out, double kick, double* act, const Coeffs& c,
+                      ForceOut mode, const Workspace& w, hipStream_t s) {
+  if (factored) {
     T* S8 = static_cast<T*>(w.staples);
     hipError_t e = timed("staples", s, [&] { return sym::launch_staples<T>(g, U, S8, s); });
     if (e != hipSuccess) return e;
@@ -167,35 +196,42 @@ hipError_t force_into(const Geom& g, const T* U, T* out, double kick, double* ac
   return timed("force_direct", s, [&] { return sym::launch_force_direct<T>(g, U, out, kick, act, c, mode, s); });
 }
 
-int force_tiles(const Geom& g) { return use_factored() ? sym::factored_tiles(g) : sym::link_tiles(g); }
-int force_kind() { return use_factored() ? 2 : 0; }
+int force_tiles(bool factored, const Geom& g) { return factored ? sym::factored_tiles(g) : sym::link_tiles(g); }
+int force_kind(bool factored) { return factored ? 2 : 0; }
+
+// The factored kernels fold the short-side rectangles and the cube loops into one
+// c-weighted partial; W_C is recovered from it by dividing by c_C, which is impossible
+// when c_C = 0 (u0 = 1, or an override). The action kernel then supplies S and W.
+bool fused_action_ok(bool factored, const Coeffs& c) { return !factored || c.c[2] != 0.0; }
 
 template <typename T>
-int do_force(const Geom& g, const Coeffs& c, const void* U, void* F, double* S_dev, const Workspace& w,
-             hipStream_t s) {
-  hipError_t e = force_into<T>(g, static_cast<const T*>(U), static_cast<T*>(F), 0.0, S_dev ? w.act : nullptr, c,
-                               ForceOut::Store, w, s);
-  if (e == hipSuccess && S_dev)
-    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, force_tiles(g), force_kind(), g, c, S_dev, s); });
-  return hip_status(e);
+hipError_t action_into(const Geom& g, const Coeffs& c, const T* U, double* S_dev, const Workspace& w, hipStream_t s) {
+  hipError_t e = timed("action", s, [&] { return sym::launch_action<T>(g, U, w.act, s); });
+  if (e == hipSuccess)
+    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, sym::action_tiles(g), 1, g, c, S_dev, s); });
+  return e;
 }
 
+// Force (Store) or gradient (Grad) of one lattice, with the action from the fused
+// partials of the same pass when they determine it, else from the action kernel.
 template <typename T>
-int do_action_grad(const Geom& g, const Coeffs& c, const void* U, void* grad, double* S_dev, const Workspace& w,
-                   hipStream_t s) {
-  hipError_t e = force_into<T>(g, static_cast<const T*>(U), static_cast<T*>(grad), 0.0, S_dev ? w.act : nullptr, c,
-                               ForceOut::Grad, w, s);
-  if (e == hipSuccess && S_dev)
-    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, force_tiles(g), force_kind(), g, c, S_dev, s); });
+int do_force(bool factored, const Geom& g, const Coeffs& c, const void* Uv, void* out, double* S_dev, ForceOut mode,
+             const Workspace& w, hipStream_t s) {
+  const T* U = static_cast<const T*>(Uv);
+  const bool fused = S_dev != nullptr && fused_action_ok(factored, c);
+  hipError_t e = force_into<T>(factored, g, U, static_cast<T*>(out), 0.0, fused ? w.act : nullptr, c, mode, w, s);
+  if (e == hipSuccess && fused)
+    e = timed("finish", s, [&] {
+      return sym::launch_finish_action(w.act, force_tiles(factored, g), force_kind(factored), g, c, S_dev, s);
+    });
+  else if (e == hipSuccess && S_dev)
+    e = action_into<T>(g, c, U, S_dev, w, s);
   return hip_status(e);
 }
 
 template <typename T>
 int do_action(const Geom& g, const Coeffs& c, const void* U, double* S_dev, const Workspace& w, hipStream_t s) {
-  hipError_t e = timed("action", s, [&] { return sym::launch_action<T>(g, static_cast<const T*>(U), w.act, s); });
-  if (e == hipSuccess)
-    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, sym::action_tiles(g), 1, g, c, S_dev, s); });
-  return hip_status(e);
+  return hip_status(action_into<T>(g, c, static_cast<const T*>(U), S_dev, w, s));
 }
 
 template <typename T>
@@ -211,8 +247,8 @@ hipError_t hamiltonian(const Geom& g, const Coeffs& c, const T* U, const T* P, d
 }
 
 template <typename T>
-int do_leapfrog(const Geom& g, const Coeffs& c, void* Uv, void* Pv, double dt, int nsteps, double* H_dev,
-                const Workspace& w, hipStream_t s) {
+int do_leapfrog(bool factored, const Geom& g, const Coeffs& c, void* Uv, void* Pv, double dt, int nsteps,
+                double* H_dev, const Workspace& w, hipStream_t s) {
   T* U = static_cast<T*>(Uv);
   T* P = static_cast<T*>(Pv);
   hipError_t e = hipSuccess;
@@ -226,19 +262,19 @@ int do_leapfrog(const Geom& g, const Coeffs& c, void* Uv, void* Pv, double dt, i
   // first kick and after the last.
   auto finish_h = [&](double* out) {
     return timed("finish", s, [&] {
-      return sym::launch_finish_hamiltonian(w.act, force_tiles(g), force_kind(), w.kin, sym::link_tiles(g), g, c,
-                                            out, s);
+      return sym::launch_finish_hamiltonian(w.act, force_tiles(factored, g), force_kind(factored), w.kin,
+                                            sym::link_tiles(g), g, c, out, s);
     });
   };
   double* act = H_dev ? w.act : nullptr;
   if (H_dev) e = timed("kinetic", s, [&] { return sym::launch_kinetic<T>(g, P, w.kin, s); });
-  if (e == hipSuccess) e = force_into<T>(g, U, P, 0.5 * dt, act, c, ForceOut::Kick, w, s);
+  if (e == hipSuccess) e = force_into<T>(factored, g, U, P, 0.5 * dt, act, c, ForceOut::Kick, w, s);
   if (H_dev && e == hipSuccess) e = finish_h(H_dev);
   for (int it = 0; it < nsteps && e == hipSuccess; ++it) {
     e = timed("drift", s, [&] { return sym::launch_drift<T>(g, U, P, dt, s); });
     if (e == hipSuccess) {
       const bool last = it + 1 == nsteps;
-      e = force_into<T>(g, U, P, last ? 0.5 * dt : dt, last ? act : nullptr, c, ForceOut::Kick, w, s);
+      e = force_into<T>(factored, g, U, P, last ? 0.5 * dt : dt, last ? act : nullptr, c, ForceOut::Kick, w, s);
     }
   }
   if (H_dev && e == hipSuccess) e = timed("kinetic", s, [&] { return sym::launch_kinetic<T>(g, P, w.kin, s); });
@@ -332,8 +368,15 @@ hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const 
     const int grid = sch.grid > 0 ? sch.grid : (sch.order == 1 ? (tiles + 7) / 8 * 8 : tiles);
     e = timed("staples_batch", s, [&] { return sym::launch_staples_batch<T>(b, grid, s); });
     if (e == hipSuccess) e = timed("force_batch", s, [&] { return sym::launch_force_batch<T>(b, grid, parts, c, s); });
-    if (e == hipSuccess && S_dev)
+    if (e == hipSuccess && S_dev && c.c[2] != 0.0)
       e = timed("finish_batch", s, [&] { return sym::launch_finish_batch(b, parts, c, S_dev + 4 * c0, s); });
+  }
+  // c_C = 0: the fused partials do not determine W_C (see fused_action_ok); the action
+  // kernel of each lattice supplies S and W, its partials in the batch partials region
+  // (a lattice has fewer action tiles than link tiles)
+  for (int i = 0; i < n && e == hipSuccess && S_dev && c.c[2] == 0.0; ++i) {
+    Workspace w{parts, nullptr, nullptr};
+    e = action_into<T>(plan.g[i], c, static_cast<const T*>(U[i]), S_dev + 4 * i, w, s);
   }
   return e;
 }
@@ -346,16 +389,29 @@ int check_batch_ptrs(int n, const void* const* U, void* const* F) {
   return SYM_OK;
 }
 
+// Every output field of a batch is disjoint from every field, from the scalars and from
+// the workspace (input fields may be shared between lattices).
+int check_batch_disjoint(int n, const BatchPlan& plan, int prec, const void* const* U, void* const* F,
+                         const double* S_dev, const void* ws) {
+  int rc;
+  for (int i = 0; i < n; ++i) {
+    const size_t ni = link_field_bytes(plan.g[i], prec);
+    if ((rc = check_disjoint({{F[i], ni}, {S_dev, 32 * (size_t)n}, {ws, plan.total}}))) return rc;
+    if ((rc = check_disjoint({{U[i], ni}, {ws, plan.total}}))) return rc;
+    for (int j = 0; j < n; ++j) {
+      const size_t nj = link_field_bytes(plan.g[j], prec);
+      if ((rc = check_disjoint({{F[i], ni}, {U[j], nj}}))) return rc;
+      if (j > i && (rc = check_disjoint({{F[i], ni}, {F[j], nj}}))) return rc;
+    }
+  }
+  return SYM_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ fat links
 
 namespace {
-
-size_t link_field_bytes(const Geom& g, int prec) {
-  const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
-  return (size_t)8 * 9 * 2 * real * (size_t)g.Vh;  // 4 directions x 2 parities x 9 complex
-}
 
 size_t fat_ws_bytes(const Geom& g, int prec) { return sym::fat::kFatFields * align256(link_field_bytes(g, prec)); }
 
@@ -434,6 +490,7 @@ int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, c
       (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ptr(ws)))
     return rc;
   if (ws_bytes < plan.total) return SYM_EWORKSPACE;
+  if ((rc = check_batch_disjoint(n, plan, prec, U, F, S_dev, ws))) return rc;
   Schedule sch = default_schedule(prec);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -455,6 +512,7 @@ int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec
       (rc = check_ptr(ws)))
     return rc;
   if (ws_bytes < plan.total) return SYM_EWORKSPACE;
+  if ((rc = check_batch_disjoint(n, plan, prec, U, F, nullptr, ws))) return rc;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return SYM_EHIP;
@@ -519,7 +577,8 @@ int sym_action(const int32_t L[4], double u0, double beta, int prec, const void*
   Coeffs c;
   int rc;
   if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
-      (rc = check_ptr(S_dev)) || (rc = check_ws(ws, ws_bytes, g, prec)))
+      (rc = check_ptr(S_dev)) || (rc = check_ws(ws, ws_bytes, g, prec)) ||
+      (rc = check_disjoint({{U, link_field_bytes(g, prec)}, {S_dev, 32}, {ws, ws_bytes_for(g, prec)}})))
     return rc;
   const Workspace w = carve(ws, g);
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -532,11 +591,15 @@ int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* 
   Coeffs c;
   int rc;
   if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
-      (rc = check_ptr(F)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)))
+      (rc = check_ptr(F)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)) ||
+      (rc = check_disjoint({{U, link_field_bytes(g, prec)}, {F, link_field_bytes(g, prec)}, {S_dev, 32},
+                            {ws, ws_bytes_for(g, prec)}})))
     return rc;
   const Workspace w = carve(ws, g);
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return prec == SYM_F64 ? do_force<double>(g, c, U, F, S_dev, w, s) : do_force<float>(g, c, U, F, S_dev, w, s);
+  const bool fac = use_factored();
+  return prec == SYM_F64 ? do_force<double>(fac, g, c, U, F, S_dev, ForceOut::Store, w, s)
+                         : do_force<float>(fac, g, c, U, F, S_dev, ForceOut::Store, w, s);
 }
 
 int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const void* U, void* grad, double* S_dev,
@@ -545,12 +608,15 @@ int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const 
   Coeffs c;
   int rc;
   if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
-      (rc = check_ptr(grad)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)))
+      (rc = check_ptr(grad)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)) ||
+      (rc = check_disjoint({{U, link_field_bytes(g, prec)}, {grad, link_field_bytes(g, prec)}, {S_dev, 32},
+                            {ws, ws_bytes_for(g, prec)}})))
     return rc;
   const Workspace w = carve(ws, g);
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return prec == SYM_F64 ? do_action_grad<double>(g, c, U, grad, S_dev, w, s)
-                         : do_action_grad<float>(g, c, U, grad, S_dev, w, s);
+  const bool fac = use_factored();
+  return prec == SYM_F64 ? do_force<double>(fac, g, c, U, grad, S_dev, ForceOut::Grad, w, s)
+                         : do_force<float>(fac, g, c, U, grad, S_dev, ForceOut::Grad, w, s);
 }
 
 int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,
@@ -562,10 +628,31 @@ int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, v
       (rc = check_ptr(P)) || (H_dev && (rc = check_ptr(H_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)))
     return rc;
   if (!isfinite(dt) || nsteps < 0) return SYM_EINVAL;
+  if ((rc = check_disjoint({{U, link_field_bytes(g, prec)}, {P, link_field_bytes(g, prec)}, {H_dev, 16},
+                            {ws, ws_bytes_for(g, prec)}})))
+    return rc;
   const Workspace w = carve(ws, g);
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return prec == SYM_F64 ? do_leapfrog<double>(g, c, U, P, dt, nsteps, H_dev, w, s)
-                         : do_leapfrog<float>(g, c, U, P, dt, nsteps, H_dev, w, s);
+  const bool fac = use_factored();
+  return prec == SYM_F64 ? do_leapfrog<double>(fac, g, c, U, P, dt, nsteps, H_dev, w, s)
+                         : do_leapfrog<float>(fac, g, c, U, P, dt, nsteps, H_dev, w, s);
+}
+
+int sym_check_links(const int32_t L[4], int prec, const void* U, double* out_dev, void* ws, size_t ws_bytes,
+                    sym_stream_t stream) {
+  Geom g;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = check_ptr(U)) || (rc = check_ptr(out_dev)) ||
+      (rc = check_ws(ws, ws_bytes, g, prec)) ||
+      (rc = check_disjoint({{U, link_field_bytes(g, prec)}, {out_dev, 24}, {ws, ws_bytes_for(g, prec)}})))
+    return rc;
+  const Workspace w = carve(ws, g);
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e = timed("check_links", s, [&] {
+    return prec == SYM_F64 ? sym::launch_check_links<double>(g, static_cast<const double*>(U), w.act, out_dev, s)
+                           : sym::launch_check_links<float>(g, static_cast<const float*>(U), w.act, out_dev, s);
+  });
+  return hip_status(e);
 }
 
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream) {
@@ -611,19 +698,11 @@ int sym_fat_links(const int32_t L[4], int prec, const double c[6], const void* U
       (rc = check_ptr(V)) || (W && (rc = check_ptr(W))) || (rc = check_ptr(ws)))
     return rc;
   if (ws_bytes < fat_ws_bytes(g, prec)) return SYM_EWORKSPACE;
+  const size_t nf = link_field_bytes(g, prec);
+  if ((rc = check_disjoint({{U, nf}, {V, nf}, {W, nf}, {ws, fat_ws_bytes(g, prec)}}))) return rc;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return prec == SYM_F64 ? do_fat_links<double>(g, cf, U, V, W, fat_carve<double>(ws, g, prec), s)
                          : do_fat_links<float>(g, cf, U, V, W, fat_carve<float>(ws, g, prec), s);
-}
-
-int sym_fma_probe(int prec, int32_t iters, void* out, sym_stream_t stream) {
-  int rc;
-  if ((rc = check_prec(prec)) || (rc = check_ptr(out))) return rc;
-  if (iters < 1 || iters > (1 << 20)) return SYM_EINVAL;
-  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const hipError_t e = prec == SYM_F64 ? sym::launch_fma_probe<double>(static_cast<double*>(out), iters, s)
-                                       : sym::launch_fma_probe<float>(static_cast<float*>(out), iters, s);
-  return hip_status(e);
 }
 
 int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U, const void* GV, const void* GW,
@@ -636,6 +715,13 @@ int sym_fat_force(const int32_t L[4], int prec, const double c[6], const void* U
     return rc;
   if ((mode & ~(SYM_FAT_FORCE | SYM_FAT_REUSE_LINKS)) != 0) return SYM_EINVAL;
   if (ws_bytes < fat_ws_bytes(g, prec)) return SYM_EWORKSPACE;
+  const size_t nf = link_field_bytes(g, prec);
+  // U, GV and GW are only read and may coincide; the output and the workspace may not
+  // overlap any of them
+  if ((rc = check_disjoint({{U, nf}, {out, nf}, {ws, fat_ws_bytes(g, prec)}})) ||
+      (rc = check_disjoint({{GV, nf}, {out, nf}, {ws, fat_ws_bytes(g, prec)}})) ||
+      (rc = check_disjoint({{GW, nf}, {out, nf}})))
+    return rc;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return prec == SYM_F64 ? do_fat_force<double>(g, cf, U, GV, GW, out, mode, fat_carve<double>(ws, g, prec), s)
                          : do_fat_force<float>(g, cf, U, GV, GW, out, mode, fat_carve<float>(ws, g, prec), s);
@@ -656,6 +742,13 @@ int sym_wilson_force(const int32_t L[4], int prec, double kappa, double csw, con
     return rc;
   if (!isfinite(kappa) || !isfinite(csw)) return SYM_EINVAL;
   if (ws_bytes < wilson_ws(g, prec)) return SYM_EWORKSPACE;
+  {
+    // U, X and Y are only read and may coincide; G and the workspace may not overlap them
+    const size_t nf = link_field_bytes(g, prec), nsp = nf / 3, nw = wilson_ws(g, prec);
+    if ((rc = check_disjoint({{U, nf}, {G, nf}, {ws, nw}})) || (rc = check_disjoint({{X, nsp}, {G, nf}, {ws, nw}})) ||
+        (rc = check_disjoint({{Y, nsp}, {G, nf}, {ws, nw}})))
+      return rc;
+  }
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e;
   if (prec == SYM_F64) {

@@ -108,6 +108,12 @@ hipError_t launch_finish_hamiltonian(const double* act_parts, int nact, int act_
 template <typename T>
 hipError_t launch_drift(const Geom& g, T* U, const T* P, double dt, hipStream_t s);
 
+// Link check: max over links of ||U^dagger U - 1||_F and |det U - 1| (double), and the
+// number of links with a non-finite element, into out[0..2]; partials: 3 doubles per
+// link tile.
+template <typename T>
+hipError_t launch_check_links(const Geom& g, const T* U, double* partials, double* out, hipStream_t s);
+
 // Layout conversion between array-of-structures lexicographic complex
 // (Lt,Lz,Ly,Lx,4,3,3) and the even-odd structure-of-arrays layout.
 template <typename T>
@@ -124,11 +130,5 @@ hipError_t launch_wilson_force(const Geom& g, const T* U, const T* X, const T* Y
                                double csw, hipStream_t s);
 template <typename T>
 hipError_t launch_spinor_layout(const Geom& g, const T* src, T* dst, bool pack, hipStream_t s);
-
-// FMA-rate probe (probe.hip): kProbeBlocks workgroups of 256 threads, each thread 8
-// independent chains of `iters` FMAs, one value per thread written to out.
-constexpr int kProbeBlocks = 4096;
-template <typename T>
-hipError_t launch_fma_probe(T* out, int iters, hipStream_t s);
 
 }  // namespace sym

@@ -76,38 +76,77 @@ def test_workspace_bytes(L_):
     assert L_.sym_workspace_bytes(_dims(64, 64, 64, 130), 1) == 0
 
 
-FAKE = ctypes.c_void_p(0x100000)       # aligned, never dereferenced
-MISALIGNED = ctypes.c_void_p(0x100008)
+# Aligned device-looking addresses, never dereferenced: every call below fails
+# validation first. They are 16 MiB apart, more than any 4^4 field or workspace, so that
+# only the calls meant to test overlapping regions trip the overlap check.
+FAKE = ctypes.c_void_p(0x10000000)
+FAKE2 = ctypes.c_void_p(0x11000000)
+FAKE3 = ctypes.c_void_p(0x12000000)
+FAKE4 = ctypes.c_void_p(0x13000000)
+MISALIGNED = ctypes.c_void_p(0x10000008)
 HUGE = 1 << 60
 
 
 def test_force_validation(L_):
     ok = _dims(4, 4, 4, 4)
     f = L_.sym_force
-    assert f(_dims(4, 4, 3, 4), 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
-    assert f(None, 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -2
-    assert f(ok, 0.8677, 3.0, 7, FAKE, FAKE, None, FAKE, HUGE, None) == -1
-    assert f(ok, -0.5, 3.0, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
-    assert f(ok, 0.8677, math.inf, 1, FAKE, FAKE, None, FAKE, HUGE, None) == -1
-    assert f(ok, 0.8677, 3.0, 1, None, FAKE, None, FAKE, HUGE, None) == -2
-    assert f(ok, 0.8677, 3.0, 1, FAKE, None, None, FAKE, HUGE, None) == -2
-    assert f(ok, 0.8677, 3.0, 1, MISALIGNED, FAKE, None, FAKE, HUGE, None) == -1
-    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
-    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, None, None, HUGE, None) == -2
-    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE, 16, None) == -3
+    assert f(_dims(4, 4, 3, 4), 0.8677, 3.0, 1, FAKE, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert f(None, 0.8677, 3.0, 1, FAKE, FAKE2, None, FAKE3, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 7, FAKE, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert f(ok, -0.5, 3.0, 1, FAKE, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert f(ok, 0.8677, math.inf, 1, FAKE, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, None, FAKE2, None, FAKE3, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, None, None, FAKE3, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, MISALIGNED, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, MISALIGNED, FAKE3, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, None, None, HUGE, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, None, FAKE3, 16, None) == -3
+
+
+def _at(base, off):
+    return ctypes.c_void_p(base.value + off)
+
+
+@pytest.mark.parametrize("fn", ["sym_force", "sym_action_grad"])
+def test_force_rejects_overlapping_regions(L_, fn):
+    """The force kernels read neighbouring links while they write: the output may not
+    alias or overlap the links, the scalars or the workspace."""
+    ok = _dims(4, 4, 4, 4)
+    f = getattr(L_, fn)
+    field = 4 * 4 * 4 * 4 * 4 * 18 * 4  # FP32 4^4 link field, bytes
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE, None, FAKE3, HUGE, None) == -1          # out == U
+    assert f(ok, 0.8677, 3.0, 1, FAKE, _at(FAKE, field - 16), None, FAKE3, HUGE, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, _at(FAKE2, 64), FAKE3, HUGE, None) == -1  # S inside out
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, None, _at(FAKE2, 256), HUGE, None) == -1  # ws inside out
+    assert f(ok, 0.8677, 3.0, 1, _at(FAKE3, 4096), FAKE2, None, FAKE3, HUGE, None) == -1  # U inside ws
 
 
 def test_action_and_leapfrog_validation(L_):
     ok = _dims(4, 4, 4, 4)
     a = L_.sym_action
-    assert a(ok, 0.8677, 3.0, 2, FAKE, None, FAKE, HUGE, None) == -2  # S_dev is required
-    assert a(ok, 0.8677, 3.0, 2, FAKE, FAKE, FAKE, 8, None) == -3
-    assert a(_dims(4, 4, 4, 6), 0.0, 3.0, 2, FAKE, FAKE, FAKE, HUGE, None) == -1
+    assert a(ok, 0.8677, 3.0, 2, FAKE, None, FAKE3, HUGE, None) == -2  # S_dev is required
+    assert a(ok, 0.8677, 3.0, 2, FAKE, FAKE2, FAKE3, 8, None) == -3
+    assert a(_dims(4, 4, 4, 6), 0.0, 3.0, 2, FAKE, FAKE2, FAKE3, HUGE, None) == -1
+    assert a(ok, 0.8677, 3.0, 2, FAKE, _at(FAKE3, 64), FAKE3, HUGE, None) == -1  # S inside ws
     m = L_.md_leapfrog
-    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, math.nan, 3, None, FAKE, HUGE, None) == -1
-    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, 0.01, -1, None, FAKE, HUGE, None) == -1
-    assert m(ok, 0.8677, 3.0, 2, FAKE, None, 0.01, 3, None, FAKE, HUGE, None) == -2
-    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, 0.01, 3, None, FAKE, 0, None) == -3
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE2, math.nan, 3, None, FAKE3, HUGE, None) == -1
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE2, 0.01, -1, None, FAKE3, HUGE, None) == -1
+    assert m(ok, 0.8677, 3.0, 2, FAKE, None, 0.01, 3, None, FAKE3, HUGE, None) == -2
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE2, 0.01, 3, None, FAKE3, 0, None) == -3
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE, 0.01, 3, None, FAKE3, HUGE, None) == -1   # P == U
+    assert m(ok, 0.8677, 3.0, 2, FAKE, _at(FAKE, 1024), 0.01, 3, None, FAKE3, HUGE, None) == -1
+    assert m(ok, 0.8677, 3.0, 2, FAKE, FAKE2, 0.01, 3, _at(FAKE, 16), FAKE3, HUGE, None) == -1  # H inside U
+
+
+def test_check_links_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    c = L_.sym_check_links
+    assert c(_dims(4, 4, 4, 5), 1, FAKE, FAKE2, FAKE3, HUGE, None) == -1
+    assert c(ok, 3, FAKE, FAKE2, FAKE3, HUGE, None) == -1
+    assert c(ok, 1, None, FAKE2, FAKE3, HUGE, None) == -2
+    assert c(ok, 1, FAKE, None, FAKE3, HUGE, None) == -2
+    assert c(ok, 1, FAKE, FAKE2, FAKE3, 8, None) == -3
+    assert c(ok, 1, FAKE, _at(FAKE, 32), FAKE3, HUGE, None) == -1
 
 
 def test_layout_and_switch_validation(L_):
@@ -132,19 +171,22 @@ def test_fat_validation(L_):
     assert L_.sym_fat_workspace_bytes(ok, 2) >= 2 * 19 * 4 * 256 * 9 * 8
     assert L_.sym_fat_workspace_bytes(_dims(4, 4, 4, 3), 1) == 0
     fl = L_.sym_fat_links
-    assert fl(ok, 1, None, FAKE, FAKE, None, FAKE, HUGE, None) == -2
+    assert fl(ok, 1, None, FAKE, FAKE2, None, FAKE3, HUGE, None) == -2
     bad = (ctypes.c_double * 6)(1, 0, 0, math.inf, 0, 0)
-    assert fl(ok, 1, bad, FAKE, FAKE, None, FAKE, HUGE, None) == -1
-    assert fl(ok, 1, c, FAKE, None, None, FAKE, HUGE, None) == -2
-    assert fl(ok, 1, c, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
-    assert fl(ok, 1, c, FAKE, FAKE, None, FAKE, 64, None) == -3
+    assert fl(ok, 1, bad, FAKE, FAKE2, None, FAKE3, HUGE, None) == -1
+    assert fl(ok, 1, c, FAKE, None, None, FAKE3, HUGE, None) == -2
+    assert fl(ok, 1, c, FAKE, FAKE2, MISALIGNED, FAKE3, HUGE, None) == -1
+    assert fl(ok, 1, c, FAKE, FAKE2, None, FAKE3, 64, None) == -3
+    assert fl(ok, 1, c, FAKE, FAKE, None, FAKE3, HUGE, None) == -1     # V == U
+    assert fl(ok, 1, c, FAKE, FAKE2, FAKE2, FAKE3, HUGE, None) == -1   # W == V
     ff = L_.sym_fat_force
-    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, 4, FAKE, HUGE, None) == -1   # mode
-    assert ff(ok, 1, c, FAKE, FAKE, None, FAKE, -1, FAKE, HUGE, None) == -1
-    assert ff(ok, 1, c, FAKE, None, None, FAKE, 0, FAKE, HUGE, None) == -2   # GV required
-    assert ff(ok, 1, c, FAKE, FAKE, None, None, 0, FAKE, HUGE, None) == -2   # out required
-    assert ff(ok, 3, c, FAKE, FAKE, None, FAKE, 0, FAKE, HUGE, None) == -1
-    assert ff(ok, 2, c, FAKE, FAKE, FAKE, FAKE, 1, FAKE, 8, None) == -3
+    assert ff(ok, 1, c, FAKE, FAKE2, None, FAKE4, 4, FAKE3, HUGE, None) == -1   # mode
+    assert ff(ok, 1, c, FAKE, FAKE2, None, FAKE4, -1, FAKE3, HUGE, None) == -1
+    assert ff(ok, 1, c, FAKE, None, None, FAKE4, 0, FAKE3, HUGE, None) == -2   # GV required
+    assert ff(ok, 1, c, FAKE, FAKE2, None, None, 0, FAKE3, HUGE, None) == -2   # out required
+    assert ff(ok, 3, c, FAKE, FAKE2, None, FAKE4, 0, FAKE3, HUGE, None) == -1
+    assert ff(ok, 2, c, FAKE, FAKE2, FAKE2, FAKE4, 1, FAKE3, 8, None) == -3
+    assert ff(ok, 1, c, FAKE, FAKE2, None, FAKE2, 0, FAKE3, HUGE, None) == -1  # out == GV
 
 
 def test_wilson_validation(L_):
@@ -152,43 +194,59 @@ def test_wilson_validation(L_):
     assert L_.sym_wilson_workspace_bytes(ok, 1) >= 2 * 6 * 9 * 128 * 4
     assert L_.sym_wilson_workspace_bytes(_dims(4, 4, 5, 4), 1) == 0
     w = L_.sym_wilson_force
-    assert w(ok, 1, math.nan, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, HUGE, None) == -1
-    assert w(ok, 1, 0.12, math.inf, FAKE, FAKE, FAKE, FAKE, FAKE, HUGE, None) == -1
-    assert w(ok, 1, 0.12, 1.0, FAKE, None, FAKE, FAKE, FAKE, HUGE, None) == -2
-    assert w(ok, 1, 0.12, 1.0, FAKE, FAKE, FAKE, MISALIGNED, FAKE, HUGE, None) == -1
-    assert w(ok, 1, 0.12, 1.0, FAKE, FAKE, FAKE, FAKE, FAKE, 16, None) == -3
-    assert L_.sym_pack_spinor(_dims(4, 4, 4, 3), 1, FAKE, FAKE, None) == -1
-    assert L_.sym_unpack_spinor(ok, 1, None, FAKE, None) == -2
+    X, Y = ctypes.c_void_p(0x14000000), ctypes.c_void_p(0x15000000)
+    assert w(ok, 1, math.nan, 1.0, FAKE, X, Y, FAKE2, FAKE3, HUGE, None) == -1
+    assert w(ok, 1, 0.12, math.inf, FAKE, X, Y, FAKE2, FAKE3, HUGE, None) == -1
+    assert w(ok, 1, 0.12, 1.0, FAKE, None, Y, FAKE2, FAKE3, HUGE, None) == -2
+    assert w(ok, 1, 0.12, 1.0, FAKE, X, Y, MISALIGNED, FAKE3, HUGE, None) == -1
+    assert w(ok, 1, 0.12, 1.0, FAKE, X, Y, FAKE2, FAKE3, 16, None) == -3
+    assert w(ok, 1, 0.12, 1.0, FAKE, X, Y, X, FAKE3, HUGE, None) == -1   # G == X
+    assert L_.sym_pack_spinor(_dims(4, 4, 4, 3), 1, FAKE, FAKE2, None) == -1
+    assert L_.sym_unpack_spinor(ok, 1, None, FAKE2, None) == -2
 
 
-def test_fma_probe_validation(L_):
-    assert L_.sym_fma_probe(3, 16, FAKE, None) == -1
-    assert L_.sym_fma_probe(1, 0, FAKE, None) == -1
-    assert L_.sym_fma_probe(1, (1 << 20) + 1, FAKE, None) == -1
-    assert L_.sym_fma_probe(2, 16, None, None) == -2
+def test_probe_library_is_separate(L_):
+    """The benchmark's FMA-rate probe lives in libsymprobe.so, outside the libsym ABI."""
+    assert not hasattr(L_, "sym_fma_probe")
+    path = os.path.join(ROOT, "paper_1808_02281_amd", "libsymprobe.so")
+    P = ctypes.CDLL(path)
+    P.probe_fma.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert P.probe_fma(3, 16, FAKE, None) == -1
+    assert P.probe_fma(1, 0, FAKE, None) == -1
+    assert P.probe_fma(1, (1 << 20) + 1, FAKE, None) == -1
+    assert P.probe_fma(1, 16, MISALIGNED, None) == -1
+    assert P.probe_fma(2, 16, None, None) == -2
 
 
 def test_batch_validation(L_):
     """Every call below is rejected before anything is launched."""
     two = (ctypes.c_int32 * 8)(4, 4, 4, 4, 6, 6, 6, 8)
     bad = (ctypes.c_int32 * 8)(4, 4, 4, 4, 6, 6, 5, 8)
-    ptrs = (ctypes.c_void_p * 2)(0x100000, 0x200000)
-    holes = (ctypes.c_void_p * 2)(0x100000, None)
+    ptrs = (ctypes.c_void_p * 2)(0x10000000, 0x11000000)
+    outs = (ctypes.c_void_p * 2)(0x12000000, 0x13000000)
+    holes = (ctypes.c_void_p * 2)(0x10000000, None)
+    WS = ctypes.c_void_p(0x20000000)
     wb = L_.sym_batch_workspace_bytes
     assert wb(2, two, 1) > 0 and wb(2, two, 2) > wb(2, two, 1)
     assert wb(0, two, 1) == 0 and wb(2, bad, 1) == 0 and wb(2, None, 1) == 0 and wb(2, two, 3) == 0
     fb = L_.sym_force_batch
-    assert fb(0, two, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
-    assert fb(2, bad, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
-    assert fb(2, None, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -2
-    assert fb(2, two, -1.0, 3.0, 1, ptrs, ptrs, None, FAKE, HUGE, None) == -1
-    assert fb(2, two, 0.8677, 3.0, 1, holes, ptrs, None, FAKE, HUGE, None) == -2
-    assert fb(2, two, 0.8677, 3.0, 1, ptrs, None, None, FAKE, HUGE, None) == -2
-    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, MISALIGNED, FAKE, HUGE, None) == -1
-    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, None, HUGE, None) == -2
-    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, FAKE, 64, None) == -3
+    assert fb(0, two, 0.8677, 3.0, 1, ptrs, outs, None, WS, HUGE, None) == -1
+    assert fb(2, bad, 0.8677, 3.0, 1, ptrs, outs, None, WS, HUGE, None) == -1
+    assert fb(2, None, 0.8677, 3.0, 1, ptrs, outs, None, WS, HUGE, None) == -2
+    assert fb(2, two, -1.0, 3.0, 1, ptrs, outs, None, WS, HUGE, None) == -1
+    assert fb(2, two, 0.8677, 3.0, 1, holes, outs, None, WS, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, None, None, WS, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, outs, MISALIGNED, WS, HUGE, None) == -1
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, outs, None, None, HUGE, None) == -2
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, outs, None, WS, 64, None) == -3
     at = L_.sym_batch_autotune
-    assert at(0, two, 0.8677, 3.0, 1, ptrs, ptrs, FAKE, HUGE, None, None, None) == -1
-    assert at(2, two, 0.8677, 3.0, 2, holes, ptrs, FAKE, HUGE, None, None, None) == -2
-    assert at(2, two, 0.8677, 3.0, 1, ptrs, ptrs, FAKE, 64, None, None, None) == -3
-
+    assert at(0, two, 0.8677, 3.0, 1, ptrs, outs, WS, HUGE, None, None, None) == -1
+    assert at(2, two, 0.8677, 3.0, 2, holes, outs, WS, HUGE, None, None, None) == -2
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, outs, WS, 64, None, None, None) == -3
+    # an output aliasing an input of another lattice, or two outputs coinciding
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, WS, HUGE, None) == -1
+    crossed = (ctypes.c_void_p * 2)(0x12000000, 0x10000000)
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, crossed, None, WS, HUGE, None) == -1
+    same = (ctypes.c_void_p * 2)(0x12000000, 0x12000000)
+    assert fb(2, two, 0.8677, 3.0, 1, ptrs, same, None, WS, HUGE, None) == -1
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, same, WS, HUGE, None, None, None) == -1

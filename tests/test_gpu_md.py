@@ -11,7 +11,7 @@ import torch
 import gaugegen
 import oracle
 
-from gpu_util import device, from_soa, rounded, to_soa
+from gpu_util import device, force_errors, from_soa, rounded, to_soa
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,33 @@ def test_trajectory_energy_change_24x24x24x48(sym, cfg4, prec):
         assert np.abs(Ue[idx] - ref).max() <= 1e-12
     else:
         assert abs(dH - gold["dH"]) <= 1e-6 * gold["H_start"]
+
+
+def test_long_fp32_chain_stays_special_unitary(sym, c):
+    """500 FP32 leapfrog steps on 8^4 (five trajectories of 100 steps, dt = 0.02, fresh
+    Gaussian momenta each): the drift projects every updated link onto SU(3) before
+    rounding, so the unitarity defect stays at float rounding, and the factored force
+    (which rebuilds third rows) agrees with the direct force (which reads every
+    element) and with the oracle on the drifted links at the FP32 gate."""
+    L = (8, 8, 8, 8)
+    dev = device()
+    Us = to_soa(sym, gaugegen.near_thermal_links(L, 0.3, 21), L, "f32", dev)
+    for traj in range(5):
+        Ps = to_soa(sym, gaugegen.momenta(L, 100 + traj), L, "f32", dev)
+        H = sym.md_leapfrog(Us, Ps, L, U0, BETA, 0.02, 100).cpu().numpy()
+        assert np.isfinite(H).all()
+        chk = sym.check_links(Us, L).cpu().numpy()
+        print(f"  trajectory {traj}: dH {H[1] - H[0]:.3e}, max |U^+U - 1| {chk[0]:.2e}, max |det U - 1| {chk[1]:.2e}",
+              flush=True)
+        assert chk[0] <= 1e-6 and chk[1] <= 1e-6 and chk[2] == 0
+    sym.set_force_algorithm("direct")
+    Fd = from_soa(sym, sym.force(Us, L, U0, BETA), L)
+    sym.set_force_algorithm("factored")
+    Ff = from_soa(sym, sym.force(Us, L, U0, BETA), L)
+    sym.set_force_algorithm("auto")
+    Ud = from_soa(sym, Us, L)
+    G_ref = oracle.force(Ud, L, c, BETA)
+    e_fd = force_errors(Ff, Fd)[0]
+    e_f, e_d = force_errors(Ff, G_ref)[0], force_errors(Fd, G_ref)[0]
+    print(f"  after 500 steps: factored vs direct {e_fd:.2e}, factored vs oracle {e_f:.2e}, direct vs oracle {e_d:.2e}")
+    assert max(e_fd, e_f, e_d) <= 1e-5

@@ -202,7 +202,7 @@ def test_parity_16x16x16x32(sym, c, alg, prec):
     assert abs(Sa[0] - S_ref) <= TOL[prec] * abs(S_ref)
 
 
-# -------------------------------------------- 32^3 x 64 (config 3), sampled
+# --------------------------------------------- 32^3 x 64 (config 3), every link
 
 @pytest.fixture(scope="module")
 def big_field():
@@ -210,35 +210,104 @@ def big_field():
     return cfg["L"], gaugegen.near_thermal_links(cfg["L"], cfg["eps"], cfg["seed"])
 
 
+@pytest.fixture(scope="module")
+def big_oracle(c, big_field):
+    """The oracle's force and action on the unrounded FP64 links (every link)."""
+    L, U = big_field
+    return oracle.force(U, L, c, BETA), oracle.action(U, L, c, BETA)[0]
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_parity_32x32x32x64_sampled(sym, c, big_field, prec):
-    """Full-size force in the launch configuration the benchmark times (auto algorithm),
-    checked on 1024 sampled links and on the whole-lattice action; every link checked for
-    tracelessness and antihermiticity."""
-    print(f"case thermal_32x32x32x64 {prec}", flush=True)
+def test_parity_32x32x32x64_every_link(sym, c, big_field, big_oracle, prec):
+    """The benchmark workload in the launch configuration the benchmark times (auto
+    algorithm), compared with the oracle on all 8,388,608 links and on the action.
+    FP32 is gated against the oracle on the same FP32-rounded links and, end to end,
+    against the oracle on the unrounded links, both at 1e-5."""
+    print(f"case thermal_32x32x32x64 {prec} every link", flush=True)
     sym.set_force_algorithm("auto")
     L, U = big_field
-    Ur = rounded(U, prec)
+    G_u, S_u = big_oracle
     dev = device()
     Us = to_soa(sym, U, L, prec, dev)
     F, S = sym.force(Us, L, U0, BETA, with_action=True)
-    G = sym.unpack(F, L)
-    # structure of every link, on the device
-    Gd = G.to(torch.complex128)
-    herm = torch.abs(Gd + Gd.conj().transpose(-1, -2)).max().item()
-    trace = torch.abs(Gd.diagonal(dim1=-2, dim2=-1).sum(-1)).max().item()
-    scale = torch.abs(Gd).max().item()
-    assert herm <= 1e-15 * scale * (1e8 if prec == "f32" else 1)
-    assert trace <= 1e-14 * scale * (1e8 if prec == "f32" else 1)
-    V = int(np.prod(L))
-    rng = np.random.default_rng(2024)
-    sites = rng.integers(0, V, 1024)
-    mus = rng.integers(0, 4, 1024)
-    G_ref = oracle.force_links(Ur, L, c, BETA, sites, mus)
-    Gs = G.reshape(V, 4, 3, 3)[torch.from_numpy(sites).to(dev), torch.from_numpy(mus).to(dev)]
-    gmax, rms, worst = force_errors(Gs.cpu().numpy().astype(np.complex128), G_ref)
-    S_ref, _ = oracle.action(Ur, L, c, BETA)
+    G = from_soa(sym, F, L)
+    del F, Us
+    if prec == "f64":
+        G_ref, S_ref = G_u, S_u
+    else:
+        Ur = rounded(U, prec)
+        G_ref, S_ref = oracle.force(Ur, L, c, BETA), oracle.action(Ur, L, c, BETA)[0]
+        del Ur
+    gmax, rms, worst = force_errors(G, G_ref)
     serr = abs(S[0].item() - S_ref) / abs(S_ref)
-    print(f"  sampled force gmax {gmax:.2e} rms {rms:.2e} worst {worst:.2e}; action {serr:.2e}", flush=True)
+    print(f"  every link: force max {gmax:.2e} rms {rms:.2e} worst-link {worst:.2e}; action {serr:.2e}", flush=True)
     assert gmax <= TOL[prec]
     assert serr <= TOL[prec]
+    # structure of every link: antihermitian and traceless to rounding
+    scale = np.abs(G).max()
+    eps = np.finfo(np.float32 if prec == "f32" else np.float64).eps
+    assert np.abs(G + np.conj(np.swapaxes(G, -1, -2))).max() <= 8 * eps * scale
+    assert np.abs(np.trace(G, axis1=-2, axis2=-1)).max() <= 16 * eps * scale
+    if prec == "f32":
+        e2e = force_errors(G, G_u)
+        se2e = abs(S[0].item() - S_u) / abs(S_u)
+        print(f"  end to end (unrounded links): force max {e2e[0]:.2e} rms {e2e[1]:.2e}; action {se2e:.2e}",
+              flush=True)
+        assert e2e[0] <= TOL[prec]
+        assert se2e <= TOL[prec]
+
+
+# ------------------------------------------- fused action with c_cube = 0
+
+@pytest.mark.parametrize("alg", ["direct", "factored"])
+def test_fused_action_with_zero_cube_coefficient(sym, alg):
+    """u0 = 1 gives alpha_s = 0, hence c_cube = 0: the factored partials cannot separate
+    W_C, and the action kernel supplies S and W. Every output is finite and equals the
+    oracle's (single lattice and batch)."""
+    sym.set_force_algorithm(alg)
+    L = (4, 6, 4, 8)
+    U = gaugegen.near_thermal_links(L, 0.4, 31)
+    c1, _ = oracle.coeffs(1.0)
+    assert c1[2] == 0.0
+    S_ref, W_ref = oracle.action(U, L, c1, BETA)
+    G_ref = oracle.force(U, L, c1, BETA)
+    dev = device()
+    Us = to_soa(sym, U, L, "f64", dev)
+    F, S = sym.force(Us, L, 1.0, BETA, with_action=True)
+    S = S.cpu().numpy()
+    assert np.isfinite(S).all()
+    assert abs(S[0] - S_ref) <= 1e-12 * abs(S_ref)
+    np.testing.assert_allclose(S[1:], W_ref, rtol=1e-12)
+    assert force_errors(from_soa(sym, F, L), G_ref)[0] <= 1e-12
+    gr, Sg = sym.action_grad(Us, L, 1.0, BETA, with_action=True)
+    np.testing.assert_allclose(Sg.cpu().numpy(), S, rtol=1e-12)
+    Fs, Sb = sym.force_batch([Us, Us], [L, L], 1.0, BETA, with_action=True)
+    Sb = Sb.cpu().numpy()
+    assert np.isfinite(Sb).all()
+    for k in range(2):
+        np.testing.assert_allclose(Sb[k], S, rtol=1e-12)
+    sym.set_force_algorithm("auto")
+
+
+# ------------------------------------------------------------- link check
+
+def test_check_links(sym):
+    """sym_check_links: max unitarity defect, max |det - 1| and the count of non-finite
+    links, on fields whose answers are known."""
+    L = (4, 4, 4, 6)
+    dev = device()
+    out = sym.check_links(to_soa(sym, gaugegen.unit_links(L), L, "f64", dev), L).cpu().numpy()
+    assert out.tolist() == [0.0, 0.0, 0.0]
+    U = gaugegen.haar_links(L, 12)
+    out = sym.check_links(to_soa(sym, U, L, "f64", dev), L).cpu().numpy()
+    assert out[0] <= 1e-14 and out[1] <= 1e-14 and out[2] == 0
+    out = sym.check_links(to_soa(sym, U, L, "f32", dev), L).cpu().numpy()
+    assert 1e-9 < out[0] <= 2e-6 and out[1] <= 2e-6 and out[2] == 0
+    V = U.copy()
+    V[1, 2, 3, 0, 2] *= 1.01           # ||U^+U - 1||_F = (1.01^2 - 1) sqrt(3), det - 1 = 1.01^3 - 1
+    V[3, 0, 1, 2, 1, 0, 2] = np.nan
+    V[0, 0, 0, 1, 3, 2, 2] = np.inf
+    out = sym.check_links(to_soa(sym, V, L, "f64", dev), L).cpu().numpy()
+    assert abs(out[0] - (1.01 ** 2 - 1) * np.sqrt(3)) <= 1e-12
+    assert abs(out[1] - (1.01 ** 3 - 1)) <= 1e-12
+    assert out[2] == 2
