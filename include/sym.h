@@ -103,6 +103,22 @@ int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* 
               size_t ws_bytes, sym_stream_t stream);
 
 /*
+ * sym_force for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same computation
+ * and result as sym_force with the same arguments, with no ws argument. Its workspace is
+ * a fixed 64 MiB array inside the library's device image, one per GPU, created with the
+ * library's device code on that GPU and held until the process ends; no call allocates.
+ * A lattice whose sym_workspace_bytes(L, prec) exceeds 64 MiB gives SYM_EWORKSPACE (about
+ * 384 bytes per link in FP32 and 768 in FP64: up to 14^4 in FP32 and 12^4 in FP64; larger
+ * lattices use sym_force with a caller workspace). Every call on one GPU uses that
+ * GPU's array, whatever the stream: calls that overlap in time on one GPU race and give
+ * wrong results; serialise them (e.g. one stream). The array needs no clearing: every
+ * call overwrites what it reads.
+ */
+int sym_force_static(const int32_t L[4], double u0, double beta, int prec, const void* U, void* F, double* S_dev,
+                     sym_stream_t stream);
+
+/*
  * Gradient of S_G with respect to the link field, for automatic differentiation:
  * grad = 2 G U per link (G as in sym_force), the representative of dS/dU on the tangent
  * space of SU(3) at U. It satisfies dS = Re tr(grad^dagger dU) for every dU = i X U

@@ -21,6 +21,7 @@ EXPORTS = (
     "sym_workspace_bytes",
     "sym_action",
     "sym_force",
+    "sym_force_static",
     "sym_action_grad",
     "md_leapfrog",
     "sym_pack",
@@ -74,6 +75,8 @@ def lib():
     L.sym_action.restype = ctypes.c_int
     L.sym_force.argtypes = [i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.sym_force.restype = ctypes.c_int
+    L.sym_force_static.argtypes = [i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+    L.sym_force_static.restype = ctypes.c_int
     L.sym_action_grad.argtypes = [i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp,
                                   ctypes.c_size_t, vp]
     L.sym_action_grad.restype = ctypes.c_int

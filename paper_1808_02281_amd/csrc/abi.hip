@@ -109,6 +109,32 @@ int check_ws(void* ws, size_t ws_bytes, const Geom& g, int prec) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SYM_OK : SYM_EHIP; }
 
+// ------------------------------------------------------ static scratch memory
+// Workspace of sym_force_static, for callers that cannot allocate device memory: a
+// fixed array in the library's device image, one copy per GPU, held until the process
+// ends. In host code `scratch` only names the symbol; its device address on the current
+// GPU comes from hipGetSymbolAddress, taken once per device on the first call there
+// and kept. Every call on one GPU shares that GPU's copy.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SYM_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return SYM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SYM_OK;
+}
+
 size_t link_field_bytes(const Geom& g, int prec) {
   const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
   return (size_t)8 * 9 * 2 * real * (size_t)g.Vh;  // 4 directions x 2 parities x 9 complex
@@ -593,6 +619,27 @@ int sym_force(const int32_t L[4], double u0, double beta, int prec, const void* 
   if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
       (rc = check_ptr(F)) || (S_dev && (rc = check_ptr(S_dev))) || (rc = check_ws(ws, ws_bytes, g, prec)) ||
       (rc = check_disjoint({{U, link_field_bytes(g, prec)}, {F, link_field_bytes(g, prec)}, {S_dev, 32},
+                            {ws, ws_bytes_for(g, prec)}})))
+    return rc;
+  const Workspace w = carve(ws, g);
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool fac = use_factored();
+  return prec == SYM_F64 ? do_force<double>(fac, g, c, U, F, S_dev, ForceOut::Store, w, s)
+                         : do_force<float>(fac, g, c, U, F, S_dev, ForceOut::Store, w, s);
+}
+
+int sym_force_static(const int32_t L[4], double u0, double beta, int prec, const void* U, void* F, double* S_dev,
+                     sym_stream_t stream) {
+  Geom g;
+  Coeffs c;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_ptr(U)) ||
+      (rc = check_ptr(F)) || (S_dev && (rc = check_ptr(S_dev))))
+    return rc;
+  if (ws_bytes_for(g, prec) > kStaticScratchBytes) return SYM_EWORKSPACE;
+  void* ws = nullptr;
+  if ((rc = static_scratch(&ws))) return rc;
+  if ((rc = check_disjoint({{U, link_field_bytes(g, prec)}, {F, link_field_bytes(g, prec)}, {S_dev, 32},
                             {ws, ws_bytes_for(g, prec)}})))
     return rc;
   const Workspace w = carve(ws, g);

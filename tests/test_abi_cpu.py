@@ -250,3 +250,21 @@ def test_batch_validation(L_):
     same = (ctypes.c_void_p * 2)(0x12000000, 0x12000000)
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, same, None, WS, HUGE, None) == -1
     assert at(2, two, 0.8677, 3.0, 1, ptrs, same, WS, HUGE, None, None, None) == -1
+
+
+def test_static_force_validation(L_):
+    """sym_force_static (no workspace argument) validates like sym_force and rejects a
+    lattice whose workspace exceeds its fixed 64 MiB array before touching the device."""
+    ok = _dims(4, 4, 4, 4)
+    f = L_.sym_force_static
+    assert f(_dims(4, 4, 3, 4), 0.8677, 3.0, 1, FAKE, FAKE2, None, None) == -1
+    assert f(None, 0.8677, 3.0, 1, FAKE, FAKE2, None, None) == -2
+    assert f(ok, 0.8677, 3.0, 7, FAKE, FAKE2, None, None) == -1
+    assert f(ok, 0.0, 3.0, 1, FAKE, FAKE2, None, None) == -1
+    assert f(ok, 0.8677, 3.0, 1, None, FAKE2, None, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, None, None, None) == -2
+    assert f(ok, 0.8677, 3.0, 1, FAKE, FAKE2, MISALIGNED, None) == -1
+    assert f(_dims(16, 16, 16, 16), 0.8677, 3.0, 1, FAKE, FAKE2, None, None) == -3
+    assert f(_dims(14, 14, 14, 14), 0.8677, 3.0, 2, FAKE, FAKE2, None, None) == -3
+    assert L_.sym_workspace_bytes(_dims(14, 14, 14, 14), 1) <= 64 << 20
+    assert L_.sym_workspace_bytes(_dims(12, 12, 12, 12), 2) <= 64 << 20
