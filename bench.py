@@ -542,6 +542,7 @@ def main():
     ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-clover force")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd timing")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
+    ap.add_argument("--only-f64", action="store_true", help="profiling runs: FP64 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the device peak measurements")
     args = ap.parse_args()
@@ -561,9 +562,10 @@ def main():
     import gaugegen
     import paper_1808_02281_amd as sym
 
-    if args.only_f32:
-        args.no_cpu_baseline = args.no_fp64 = args.no_md = args.no_batch = args.no_fat = True
+    if args.only_f32 or args.only_f64:
+        args.no_cpu_baseline = args.no_md = args.no_batch = args.no_fat = True
         args.no_wilson = args.no_autograd = args.no_peaks = True
+        args.no_fp64 = args.only_f32
 
     cfg = gaugegen.CONFIGS[WORKLOAD]
     L = cfg["L"]

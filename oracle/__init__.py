@@ -22,6 +22,7 @@ from .oracle import (  # noqa: F401
     kinetic,
     leapfrog,
     num_threads,
+    set_num_threads,
     FAT_CLASSES,
     fat_paths,
     fat_links,
