@@ -378,7 +378,7 @@ hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const 
     memset(&b, 0, sizeof b);
     b.n = (n - c0) < sym::kMaxBatch ? (n - c0) : sym::kMaxBatch;
     b.order = sch.order;
-    int tiles = 0;
+    int tiles = 0, site_tiles = 0;
     for (int k = 0; k < b.n; ++k) {
       const int i = c0 + k;
       sym::BatchEntry& en = b.e[k];
@@ -388,11 +388,14 @@ hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const 
       for (int a = 0; a < 4; ++a) en.L[a] = plan.g[i].L[a];
       en.Vh = plan.g[i].Vh;
       en.tile_begin = tiles;
+      en.site_tile_begin = site_tiles;
       tiles += sym::link_tiles(plan.g[i]);
+      site_tiles += sym::site_tiles(plan.g[i]);
     }
     b.total_tiles = tiles;
+    b.total_site_tiles = site_tiles;
     const int grid = sch.grid > 0 ? sch.grid : (sch.order == 1 ? (tiles + 7) / 8 * 8 : tiles);
-    e = timed("staples_batch", s, [&] { return sym::launch_staples_batch<T>(b, grid, s); });
+    e = timed("staples_batch", s, [&] { return sym::launch_staples_batch<T>(b, sch.grid, s); });
     if (e == hipSuccess) e = timed("force_batch", s, [&] { return sym::launch_force_batch<T>(b, grid, parts, c, s); });
     if (e == hipSuccess && S_dev && c.c[2] != 0.0)
       e = timed("finish_batch", s, [&] { return sym::launch_finish_batch(b, parts, c, S_dev + 4 * c0, s); });

@@ -1,31 +1,43 @@
-// Factored gauge force: per-link device code shared by the single-lattice kernels
-// (force_factored.hip) and the batched persistent kernels (force_batch.hip).
+// Factored gauge force: device code shared by the single-lattice kernels
+// (force_factored.hip) and the batched kernels (force_batch.hip).
 //
-// Factored gauge force. Same result as the direct form (every staple of
-// arXiv:1808.02281 Sec. II, eq. 18_7_25_2), with rectangle and cube staples assembled
-// from plaquette staples instead of multiplied out link by link.
+// Same result as the direct form (every staple of arXiv:1808.02281 Sec. II,
+// eq. 18_7_25_2), with rectangle and cube staples assembled from plaquette staples
+// instead of multiplied out link by link.
 //
-// Notation: for link (x, mu) and a signed direction e perpendicular to mu,
-//   S(x, mu, e) = U_{x+mu, e} U_{x+e, mu}^dagger U_{x, e}^dagger
-// is the plaquette staple (path e, -mu, -e from x+mu back to x), with
-// U_{y,-nu} = U_{y-nu,nu}^dagger. Inserting U^dagger U = 1 along the paths gives,
-// for the 42 five-link staples of link (x, mu):
+// Notation: U_{y,d} for a signed direction d is the link matrix of the step y -> y+d
+// (U_{y,-nu} = U_{y-nu,nu}^dagger). For the link at y in signed direction d and a
+// signed direction e perpendicular to it,
+//   S(y, d, e) = U_{y+d, e} U_{y+d+e, -d} U_{y+e, -e}
+// is the plaquette staple (path e, -d, -e from y+d back to y); S(y, -nu, e) =
+// S(y-nu, nu, e)^dagger. Inserting U^dagger U = 1 along the paths gives, for the 42
+// five-link staples of link (x, mu):
 //   rectangles, link first on the long side:  U_{x+mu,mu} S(x+mu,mu,e) S(x,mu,e)
 //   rectangles, link second on the long side: S(x,mu,e) S(x-mu,mu,e) U_{x-mu,mu}
-//   rectangles with the link as short side:   U_{x+mu,e} S(x+e,mu,e) U_{x,e}^dagger
-//   cube loops (e, f, -mu, -e, -f):           U_{x+mu,e} S(x+e,mu,f) S'(x,e,f)
-// where f is perpendicular to mu and to e, and S'(x,e,f) is the path f, -e, -f from
-// x+e to x: S(x,nu,f) for e = +nu, S(x-nu,nu,f)^dagger for e = -nu. Sums over e and f
-// are taken before the shared outer factors are applied.
+//   rectangles with the link as short side:   U_{x+mu,f} S(x+f,mu,f) U_{x+f,-f}
+//   cube loop (mu, e, f, -mu, -e, -f), two ways:
+//     A: U_{x+mu,e} S(x+e,mu,f) S(x,e,f)
+//     B: S(x+mu,f,e)^dagger S(x+f,mu,e) U_{x+f,-f}
+// Forms A of cube (f, e) and B of cube (e, f) share the middle staple S(x+f, mu, e).
+// Pass 2 takes, for every f (6 signed directions) and the two e along the next frame
+// axis (cyclically), cube (f, e) in form A and cube (e, f) in form B; this covers each
+// of the 24 cube loops once (every unordered pair {e, f} once) and loads 36 staples for
+// them instead of 48, at the price of a second outer product per f:
+//   t += U_{x+mu,f} [c_R S(x+f,mu,f) U_{x+f,-f} + c_C QA_f] + c_C QB_f U_{x+f,-f},
+//   QA_f = sum_e S(x+f,mu,e) S(x,f,e),   QB_f = sum_e S(x+mu,f,e)^dagger S(x+f,mu,e).
+// The pass is bound by the bytes its loads move through the caches (its vector memory
+// unit is busier than its ALUs), so trading six products per link for twelve staple
+// loads makes it faster: 2.79 -> 2.48 ms (FP32) and 6.55 -> 5.53 ms (FP64) on the
+// 32^3 x 64 workload.
 //
-// Pass 1 (staples_kernel) writes the six S(x,mu,e) of every link to the workspace:
-// 12 SU(3) products per link, each link read as its first two rows (the third rebuilt),
-// which cuts the pass from 1.05 to 0.88 ms (FP32) and 1.93 to 1.55 ms (FP64) on the
-// 32^3 x 64 workload; the links of the short-side and cube terms of pass 2 are read
-// the same way (3.02 -> 2.92 ms FP32). Pass 2 (force_factored_kernel) reads them and forms
-//   t = c_P sum_e S + c_R (rect sums) + (c_R short-side rect + c_C cube sums):
-// 6+1 and 6+1 products for the long-side rectangles, 6 x (1 + 4 + 1) for the rest,
-// plus U t: 51 products. 63 products per link in all, against 181 for the direct form.
+// Pass 1 (staples_site) writes the 24 staples S(x, mu, e) of the four links of every
+// site, one thread per site: the two staples S(x,mu,+a) = m U_{x,a}^dagger and
+// S(x,a,+mu) = m^dagger U_{x,mu}^dagger of the plaquette at x in the plane (mu, a)
+// share m = U_{x+mu,a} U_{x+a,mu}^dagger, and the links at x and x-a serve several
+// staples, so a site loads 44 links instead of 72 (one thread per link) and forms the
+// staples with 42 products instead of 48. Each thread writes only its own site.
+// Pass 2 (factored_link) reads them and forms
+//   t = c_P sum_e S + c_R (long-side rect sums) + (c_R short-side rect + c_C cube sums).
 //
 // Action: per link the kernel emits three deficit sums
 //   a1 = 18 - Re tr(U t_P), a2 = 36 - Re tr(U t_RA+RB), a3 = 18 c_R + 72 c_C - Re tr(U t_mix)
@@ -174,123 +186,53 @@ __device__ __forceinline__ void launder(FCtx<T>& c) {
 
 // ---------------------------------------------------------------- pass 1
 
-template <typename T, int J>
-__device__ __forceinline__ su3<T> plaquette_staple(const FCtx<T>& c) {
-  constexpr int a = e_axis(J);
-  constexpr int a1 = comp(1, a), a2 = comp(2, a), a3 = comp(3, a);
-  if constexpr (e_sign(J) > 0) {
-    // U_{x+mu,a} U_{x+a,mu}^dag U_{x,a}^dag
-    const su3<T> m = mul<false, true>(c.template link_rows<1, 0, 0, 0, a>(), c.template link_rows<0, a1, a2, a3, 0>());
-    return mul<false, true>(m, c.template link_rows<0, 0, 0, 0, a>());
-  } else {
-    // U_{x+mu-a,a}^dag U_{x-a,mu}^dag U_{x-a,a}
-    const su3<T> m = mul<true, true>(c.template link_rows<1, -a1, -a2, -a3, a>(), c.template link_rows<0, -a1, -a2, -a3, 0>());
-    return mul<false, false>(m, c.template link_rows<0, -a1, -a2, -a3, a>());
-  }
-}
-
-template <typename T, int J>
-__device__ __forceinline__ void write_staples(const FCtx<T>& c, T* S8, int cb) {
-  if constexpr (J < 6) {
-    FCtx<T> lc = c;
-    launder(lc);
-    const su3<T> s = plaquette_staple<T, J>(lc);
-    const int slot = 2 * c.axis[e_axis(J)] + (e_sign(J) < 0 ? 1 : 0);
-    cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((c.axis[0] * 2 + c.p) * 8 + slot) * 6) * (size_t)c.Ss;
-    if constexpr (sizeof(T) == 4) {
-      const unsigned bytes = 6u * (unsigned)c.Ss * (unsigned)sizeof(cx<T>);
-      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)bytes, kBufferWord3);
-      const int voff = cb * (int)(2 * sizeof(cx<T>));
+// Staple store: FP32 as three planes of 16-byte element pairs, FP64 as six planes.
+template <typename T, int POL = kStoreNT>
+__device__ __forceinline__ void store_staple(T* S8, int Ss, int mu, int p, int slot, int cb, const Rows2<T>& s) {
+  cx<T>* dst = reinterpret_cast<cx<T>*>(S8) + (size_t)(((mu * 2 + p) * 8 + slot) * 6) * (size_t)Ss;
+  const unsigned bytes = 6u * (unsigned)Ss * (unsigned)sizeof(cx<T>);
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)bytes, kBufferWord3);
+  if constexpr (sizeof(T) == 4) {
+    const int voff = cb * (int)(2 * sizeof(cx<T>));
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int soff = (int)((unsigned)q * (unsigned)c.Ss * (unsigned)(2 * sizeof(cx<T>)));
-        const CxPair<T> v{s.e[2 * q], s.e[2 * q + 1]};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), r, voff, soff, kStoreNT);
-      }
-    } else {
-      store_su3_rows(dst, c.Ss, cb, s);
+    for (int q = 0; q < 3; ++q) {
+      const int soff = (int)((unsigned)q * (unsigned)Ss * (unsigned)(2 * sizeof(cx<T>)));
+      const CxPair<T> v{s.e[2 * q], s.e[2 * q + 1]};
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), r, voff, soff, POL);
     }
-    SYM_FENCE();
-    write_staples<T, J + 1>(c, S8, cb);
-  }
-}
-
-
-// ---------------------------------------------------------------- pass 2
-
-// Short-side rectangles and cube loops, software-pipelined. For e = e_J (J = 0..5) and
-// the four f perpendicular to mu and e (cube_f(J, i)):
-//   t += U_{x+mu,e} [ c_R S(x+e,mu,e) U_{x,e}^dag + c_C sum_f S(x+e,mu,f) S'(x,e,f) ].
-// The loads of each e are split in two halves, A (two cube terms) and B (two cube terms,
-// the short-side staple and the two links); the loads of the next half are issued
-// before the current half is multiplied out, so that their latency is covered by
-// arithmetic instead of by other waves alone (FP32, 32^3 x 64 force pass: 3.26 ms in
-// plain order, 3.11 ms with the cube loop pipelined, 3.08 ms with the long-side sums
-// pipelined too, 223 VGPRs; issuing the first cube loads during the long-side epilogue
-// as well reached 256 VGPRs and was slower). FP64 takes the same form: its operands
-// need about 420 registers, so one wave per SIMD holds them in VGPRs and AGPRs
-// (6.72 ms in plain order, 6.50 ms pipelined).
-constexpr int cube_f(int J, int i) {
-  int n = 0;
-  for (int K = 0; K < 6; ++K) {
-    if (e_axis(K) != e_axis(J)) {
-      if (n == i) return K;
-      ++n;
-    }
-  }
-  return -1;
-}
-
-template <typename T>
-struct CubeA {
-  Rows2<T> l0, r0, l1, r1;
-};
-template <typename T>
-struct CubeB {
-  Rows2<T> l2, r2, l3, r3, see;
-  su3<T> lnk, uxm;
-};
-
-// S(x+e,mu,f) and S'(x,e,f) for the i-th f of e_J
-template <int J, int I, typename T>
-__device__ __forceinline__ void cube_pair(const FCtx<T>& c, Rows2<T>& l, Rows2<T>& r) {
-  constexpr int a = e_axis(J), s = e_sign(J), K = cube_f(J, I), fa = e_axis(K), fs = e_sign(K);
-  constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
-  l = c.template stap_rows<0, e1, e2, e3, 0, fa, fs>();
-  if constexpr (s > 0)
-    r = c.template stap_rows<0, 0, 0, 0, a, fa, fs>();
-  else
-    r = c.template stap_rows<0, e1, e2, e3, a, fa, fs>();
-}
-
-template <int J, typename T>
-__device__ __forceinline__ CubeA<T> load_cube_a(const FCtx<T>& c0) {
-  FCtx<T> c = c0;
-  launder(c);
-  CubeA<T> d;
-  cube_pair<J, 0>(c, d.l0, d.r0);
-  cube_pair<J, 1>(c, d.l1, d.r1);
-  return d;
-}
-
-template <int J, typename T>
-__device__ __forceinline__ CubeB<T> load_cube_b(const FCtx<T>& c0) {
-  FCtx<T> c = c0;
-  launder(c);
-  constexpr int a = e_axis(J), s = e_sign(J);
-  constexpr int e1 = s * comp(1, a), e2 = s * comp(2, a), e3 = s * comp(3, a);
-  CubeB<T> d;
-  cube_pair<J, 2>(c, d.l2, d.r2);
-  cube_pair<J, 3>(c, d.l3, d.r3);
-  d.see = c.template stap_rows<0, e1, e2, e3, 0, a, s>();
-  if constexpr (s > 0) {
-    d.lnk = c.template link_rows<0, 0, 0, 0, a>();
-    d.uxm = c.template link_rows<1, 0, 0, 0, a>();
   } else {
-    d.lnk = c.template link_rows<0, e1, e2, e3, a>();
-    d.uxm = c.template link_rows<1, e1, e2, e3, a>();
+    const int voff = cb * (int)sizeof(cx<T>);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int soff = (int)((unsigned)c * (unsigned)Ss * (unsigned)sizeof(cx<T>));
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, s.e[c]),
+                                             r, voff, soff, POL);
+    }
   }
-  return d;
+}
+
+// Rows 0, 1 of a^{DA} b^{DB} for a, b given in full.
+template <bool DA, bool DB, typename T>
+__device__ __forceinline__ Rows2<T> rows_mul2(const su3<T>& a, const su3<T>& b) {
+  Rows2<T> P;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T re = T(0), im = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const cx<T> x = elem<DA>(a, i, k);
+        const cx<T> y = elem<DB>(b, k, j);
+        re = fma(x.re, y.re, re);
+        im = fma(x.re, y.im, im);
+        re = fma(-x.im, y.im, re);
+        im = fma(x.im, y.re, im);
+      }
+      P.e[3 * i + j] = cx<T>{re, im};
+    }
+  }
+  return P;
 }
 
 // The first two rows of l r^{DB} for l given by its two stored rows and r in full; the
@@ -319,53 +261,220 @@ __device__ __forceinline__ Rows2<T> rows_mul(const Rows2<T>& l, const su3<T>& r)
   return P;
 }
 
-// Q += l r (e > 0) or l r^dagger (e < 0) for staples l, r in SU(3) given by their first
-// two rows. The product is special unitary too, so only its first two rows are
-// multiplied out (from the two stored rows of l) and its third row is rebuilt from
-// them: 18 complex multiply-adds and one rebuild instead of 27 and two.
-template <int J, typename T>
-__device__ __forceinline__ void cube_mac(su3<T>& Q, const Rows2<T>& l, const Rows2<T>& r) {
-  add(Q, full(rows_mul<(e_sign(J) < 0)>(l, full(r))));
-}
+// One thread per site: absolute directions, links of the site's neighbourhood.
+template <typename T>
+struct SCtx {
+  const T* U;
+  T* S8;
+  int Vh;
+  int Ss;
+  int p;
+  int cb;
+  Nbr nb;
 
-template <int J, typename T>
-__device__ __forceinline__ void use_cube_b(su3<T>& t, su3<T>& Q, const CubeB<T>& d, T cR, T cC) {
-  cube_mac<J>(Q, d.l2, d.r2);
-  cube_mac<J>(Q, d.l3, d.r3);
-  su3<T> R = full(rows_mul<(e_sign(J) > 0)>(d.see, d.lnk));  // S(x+e,mu,e) U_{x,e}^dag (special unitary)
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    R.e[i].re = fma(cC, Q.e[i].re, cR * R.e[i].re);
-    R.e[i].im = fma(cC, Q.e[i].im, cR * R.e[i].im);
+  // U_{x+d, MU} from its first two rows (special unitary)
+  template <int MU, int D0, int D1, int D2, int D3>
+  __device__ __forceinline__ su3<T> link() const {
+    constexpr int dp = offset_parity<D0, D1, D2, D3>();
+    return load_su3_rows(block_ptr(U, MU, p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
   }
-  if constexpr (e_sign(J) > 0)
-    mac<false, false>(t, d.uxm, R);
-  else
-    mac<true, false>(t, d.uxm, R);
+};
+
+template <typename T>
+__device__ __forceinline__ void launder(SCtx<T>& c) {
+  asm volatile("" : "+s"(c.U));
+  asm volatile("" : "+s"(c.S8));
 }
 
-template <int J, typename T>
-__device__ __forceinline__ void cubes_pipe(const FCtx<T>& c, su3<T>& t, const CubeA<T>& a, const CubeB<T>& b, T cR,
-                                           T cC) {
-  su3<T> Q;
-  set_zero(Q);
-  cube_mac<J>(Q, a.l0, a.r0);
-  cube_mac<J>(Q, a.l1, a.r1);
+constexpr int unit(int axis, int a) { return axis == a ? 1 : 0; }
+
+// Staples of the plaquette at x in the plane (MU, A), MU < A: S(x,MU,+A) and S(x,A,+MU).
+template <int MU, int A, int POL, typename T>
+__device__ __forceinline__ void plane_staples(const SCtx<T>& c0, const su3<T>& uMU, const su3<T>& uA) {
+  SCtx<T> c = c0;
+  launder(c);
+  const su3<T> a = c.template link<A, unit(0, MU), unit(1, MU), unit(2, MU), unit(3, MU)>();  // U_{x+MU,A}
+  const su3<T> b = c.template link<MU, unit(0, A), unit(1, A), unit(2, A), unit(3, A)>();     // U_{x+A,MU}
+  const su3<T> m = full(rows_mul2<false, true>(a, b));  // U_{x+MU,A} U_{x+A,MU}^dagger (special unitary)
+  store_staple<T, POL>(c.S8, c.Ss, MU, c.p, 2 * A, c.cb, rows_mul2<false, true>(m, uA));
+  store_staple<T, POL>(c.S8, c.Ss, A, c.p, 2 * MU, c.cb, rows_mul2<true, true>(m, uMU));
+}
+
+// S(x, MU, -A) = U_{x+MU-A,A}^dagger U_{x-A,MU}^dagger U_{x-A,A}, with w = U_{x-A,A}.
+template <int MU, int A, int POL, typename T>
+__device__ __forceinline__ void back_staple(const SCtx<T>& c0, const su3<T>& w) {
+  SCtx<T> c = c0;
+  launder(c);
+  const su3<T> cl = c.template link<A, unit(0, MU) - unit(0, A), unit(1, MU) - unit(1, A), unit(2, MU) - unit(2, A),
+                                    unit(3, MU) - unit(3, A)>();
+  const su3<T> d = c.template link<MU, -unit(0, A), -unit(1, A), -unit(2, A), -unit(3, A)>();
+  const su3<T> n = full(rows_mul2<true, true>(cl, d));  // (U_{x-A,MU} U_{x+MU-A,A})^dagger
+  store_staple<T, POL>(c.S8, c.Ss, MU, c.p, 2 * A + 1, c.cb, rows_mul2<false, false>(n, w));
+}
+
+template <int I, int POL, typename T>
+__device__ __forceinline__ void forward_planes(const SCtx<T>& c, const su3<T> (&u)[4]) {
+  // the six planes (MU, A), MU < A
+  constexpr int MU = I < 3 ? 0 : (I < 5 ? 1 : 2);
+  constexpr int A = I < 3 ? I + 1 : (I < 5 ? I - 1 : 3);
+  if constexpr (I < 6) {
+    plane_staples<MU, A, POL>(c, u[MU], u[A]);
+    SYM_FENCE();
+    forward_planes<I + 1, POL>(c, u);
+  }
+}
+
+template <int A, int J, int POL, typename T>
+__device__ __forceinline__ void backward_staples(const SCtx<T>& c, const su3<T>& w) {
+  // the three MU != A
+  constexpr int MU = J < A ? J : J + 1;
+  if constexpr (J < 3) {
+    back_staple<MU, A, POL>(c, w);
+    SYM_FENCE();
+    backward_staples<A, J + 1, POL>(c, w);
+  }
+}
+
+template <int A, int POL, typename T>
+__device__ __forceinline__ void backward_all(const SCtx<T>& c0) {
+  if constexpr (A < 4) {
+    SCtx<T> c = c0;
+    launder(c);
+    const su3<T> w = c.template link<A, -unit(0, A), -unit(1, A), -unit(2, A), -unit(3, A)>();  // U_{x-A,A}
+    backward_staples<A, 0, POL>(c, w);
+    backward_all<A + 1, POL>(c0);
+  }
+}
+
+// Pass 1 for site (p, cb) of lattice g: the 24 staples of its four links into S8
+// (POL: cache policy of the stores).
+template <typename T, int POL = kStoreNT>
+__device__ __forceinline__ void staples_site(const Geom& g, const T* U, T* S8, int p, int cb) {
+  int x[4];
+  cb_coords(g, p, cb, x);
+  SCtx<T> c;
+  c.U = U;
+  c.S8 = S8;
+  c.Vh = g.Vh;
+  c.Ss = s8_stride(g);
+  c.p = p;
+  c.cb = cb;
+  make_nbr(g, x, c.nb);
+  {
+    su3<T> u[4];
+    u[0] = c.template link<0, 0, 0, 0, 0>();
+    u[1] = c.template link<1, 0, 0, 0, 0>();
+    u[2] = c.template link<2, 0, 0, 0, 0>();
+    u[3] = c.template link<3, 0, 0, 0, 0>();
+    SYM_FENCE();
+    forward_planes<0, POL>(c, u);
+  }
   SYM_FENCE();
-  if constexpr (J < 5) {
-    const CubeA<T> an = load_cube_a<J + 1>(c);
-    SYM_FENCE();
-    use_cube_b<J>(t, Q, b, cR, cC);
-    SYM_FENCE();
-    const CubeB<T> bn = load_cube_b<J + 1>(c);
-    SYM_FENCE();
-    cubes_pipe<J + 1>(c, t, an, bn, cR, cC);
+  backward_all<0, POL>(c);
+}
+
+
+// ---------------------------------------------------------------- pass 2
+
+// Short-side rectangles and cube loops (mixed factorisation, see the top of the file),
+// software-pipelined item by item: the loads of item K+1 are issued before item K is
+// multiplied out. Items K = 3F + k for F = 0..5 (f = e_F): k = 0, 1 the triple
+// (S(x+f,mu,e), S(x,f,e), S(x+mu,f,e)) for e = +-(next frame axis); k = 2 the short
+// side (S(x+f,mu,f), U_{x+f,-f}, U_{x+mu,f}) and the outer products of f.
+constexpr int next_axis(int a) { return a == 3 ? 1 : a + 1; }
+constexpr int kItems = 18;
+
+template <typename T>
+struct Triple {
+  Rows2<T> m, a, b;  // S(x+f,mu,e); S(x,f,e) (or its dagger's storage); S(x+mu,f,e) (likewise)
+};
+template <typename T>
+struct Short {
+  Rows2<T> see;      // S(x+f,mu,f)
+  su3<T> lnk, uxm;   // U_{x,a} or U_{x-a,a}; U_{x+mu,a} or U_{x+mu-a,a}  (f = +-a)
+};
+
+template <int K, typename T>
+__device__ __forceinline__ auto load_item(const FCtx<T>& c0) {
+  FCtx<T> c = c0;
+  launder(c);
+  constexpr int F = K / 3, k = K % 3;
+  constexpr int fa = e_axis(F), fs = e_sign(F);
+  constexpr int f1 = fs * comp(1, fa), f2 = fs * comp(2, fa), f3 = fs * comp(3, fa);
+  if constexpr (k < 2) {
+    constexpr int ea = next_axis(fa), es = k == 0 ? 1 : -1;
+    Triple<T> d;
+    d.m = c.template stap_rows<0, f1, f2, f3, 0, ea, es>();  // S(x+f, mu, e)
+    // S(x, f, e) and S(x+mu, f, e): for f = -a stored as S(x-a, a, e)^dagger and
+    // S(x+mu-a, a, e)^dagger
+    d.a = c.template stap_rows<0, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
+    d.b = c.template stap_rows<1, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
+    return d;
   } else {
-    use_cube_b<J>(t, Q, b, cR, cC);
-    SYM_FENCE();
+    Short<T> d;
+    d.see = c.template stap_rows<0, f1, f2, f3, 0, fa, fs>();
+    if constexpr (fs > 0) {
+      d.lnk = c.template link_rows<0, 0, 0, 0, fa>();
+      d.uxm = c.template link_rows<1, 0, 0, 0, fa>();
+    } else {
+      d.lnk = c.template link_rows<0, f1, f2, f3, fa>();
+      d.uxm = c.template link_rows<1, f1, f2, f3, fa>();
+    }
+    return d;
   }
 }
 
+template <int K, typename T, typename It>
+__device__ __forceinline__ void use_item(su3<T>& t, su3<T>& QA, su3<T>& QB, const It& d, T cR, T cC) {
+  constexpr int F = K / 3, k = K % 3;
+  constexpr int fs = e_sign(F);
+  if constexpr (k < 2) {
+    if constexpr (k == 0) {
+      set_zero(QA);
+      set_zero(QB);
+    }
+    // every factor is special unitary, so is every product: two rows are multiplied
+    // out and the third rebuilt
+    const su3<T> m = full(d.m);
+    if constexpr (fs > 0) {
+      add(QA, full(rows_mul<false>(d.m, full(d.a))));   // S(x+f,mu,e) S(x,a,e)
+      add(QB, full(rows_mul2<true, false>(full(d.b), m)));  // S(x+mu,a,e)^dagger S(x+f,mu,e)
+    } else {
+      add(QA, full(rows_mul<true>(d.m, full(d.a))));    // S(x+f,mu,e) S(x-a,a,e)^dagger
+      add(QB, full(rows_mul<false>(d.b, m)));           // S(x+mu-a,a,e) S(x+f,mu,e)
+    }
+  } else {
+    su3<T> R = full(rows_mul<(fs > 0)>(d.see, d.lnk));  // S(x+f,mu,f) U_{x+f,-f}
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      R.e[i].re = fma(cC, QA.e[i].re, cR * R.e[i].re);
+      R.e[i].im = fma(cC, QA.e[i].im, cR * R.e[i].im);
+      QB.e[i].re *= cC;
+      QB.e[i].im *= cC;
+    }
+    if constexpr (fs > 0) {
+      mac<false, false>(t, d.uxm, R);
+      mac<false, true>(t, QB, d.lnk);
+    } else {
+      mac<true, false>(t, d.uxm, R);
+      mac<false, false>(t, QB, d.lnk);
+    }
+  }
+}
+
+template <int K, typename T, typename It>
+__device__ __forceinline__ void items_pipe(const FCtx<T>& c, su3<T>& t, su3<T>& QA, su3<T>& QB, const It& cur, T cR,
+                                           T cC) {
+  if constexpr (K + 1 < kItems) {
+    const auto nxt = load_item<K + 1>(c);
+    SYM_FENCE();
+    use_item<K>(t, QA, QB, cur, cR, cC);
+    SYM_FENCE();
+    items_pipe<K + 1>(c, t, QA, QB, nxt, cR, cC);
+  } else {
+    use_item<K>(t, QA, QB, cur, cR, cC);
+  }
+}
 
 // Long-side rectangles, RA += S(x+mu,mu,e) S(x,mu,e), RB += S(x,mu,e) S(x-mu,mu,e),
 // tP += S(x,mu,e), software-pipelined: the three staples of e_{J+1} are requested
@@ -402,21 +511,6 @@ __device__ __forceinline__ void long_pipe(const FCtx<T>& c, su3<T>& tP, su3<T>& 
     add(RA, full(rows_mul<false>(d.sp, sx)));
     mac<false, false>(RB, sx, full(d.sm));
   }
-}
-
-// Pass 1 for link (mu, p, cb) of lattice g: its six plaquette staples into S8.
-template <typename T>
-__device__ __forceinline__ void staples_link(const Geom& g, const T* U, T* S8, int mu, int p, int cb) {
-  int x[4];
-  cb_coords(g, p, cb, x);
-  FCtx<T> c;
-  c.U = U;
-  c.S8 = S8;
-  c.Vh = g.Vh;
-  c.Ss = s8_stride(g);
-  c.p = p;
-  make_frame(g, mu, x, c.axis, c.nb);
-  write_staples<T, 0>(c, S8, cb);
 }
 
 // Pass 2 for link (mu, p, cb): force epilogue per MODE, deficit partials into a[3].
@@ -462,10 +556,10 @@ __device__ __forceinline__ void factored_link(const Geom& g, const T* U, const T
   SYM_FENCE();
   {
     // software-pipelined short-side rectangles and cube loops
-    const CubeA<T> a0 = load_cube_a<0>(c);
-    const CubeB<T> b0 = load_cube_b<0>(c);
+    su3<T> QA, QB;
+    const auto d0 = load_item<0>(c);
     SYM_FENCE();
-    cubes_pipe<0>(c, t, a0, b0, cR, cC);
+    items_pipe<0>(c, t, QA, QB, d0, cR, cC);
   }
 
   FCtx<T> lc = c;

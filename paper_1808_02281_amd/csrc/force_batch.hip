@@ -10,25 +10,28 @@ namespace sym {
 namespace {
 
 using factored::factored_link;
-using factored::staples_link;
+using factored::staples_site;
 
-// k-th tile of workgroup blk, or -1 when the workgroup has no more work.
-__device__ __forceinline__ int batch_tile(const BatchTable& b, int blk, int grid, int k) {
+// k-th tile of workgroup blk among `total` tiles, or -1 when the workgroup has no more
+// work (-2: none this round, continue).
+__device__ __forceinline__ int batch_tile(const BatchTable& b, int total, int blk, int grid, int k) {
   if (b.order == 0) {
     const int t = blk + k * grid;
-    return t < b.total_tiles ? t : -1;
+    return t < total ? t : -1;
   }
   const int gx = grid >> 3;                      // workgroups per XCD
-  const int per = (b.total_tiles + 7) >> 3;      // tiles per XCD
+  const int per = (total + 7) >> 3;              // tiles per XCD
   const int r = (blk >> 3) + k * gx;
   if (r >= per) return -1;
   const int t = (blk & 7) * per + r;
-  return t < b.total_tiles ? t : -2;
+  return t < total ? t : -2;
 }
 
+// Lattice of a link tile (SITES = false) or of a site tile (SITES = true).
+template <bool SITES>
 __device__ __forceinline__ int find_lattice(const BatchTable& b, int tile) {
   int l = 0;
-  for (int k = 1; k < b.n; ++k) l = tile >= b.e[k].tile_begin ? k : l;
+  for (int k = 1; k < b.n; ++k) l = tile >= (SITES ? b.e[k].site_tile_begin : b.e[k].tile_begin) ? k : l;
   return l;
 }
 
@@ -42,17 +45,18 @@ __device__ __forceinline__ Geom geom_of(const BatchEntry& e) {
   return g;
 }
 
+// Pass 1 over the site tiles of all lattices (two per 256-site chunk: the parities).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void staples_batch_kernel(const BatchTable b) {
   for (int k = 0;; ++k) {
-    const int tile = batch_tile(b, blockIdx.x, gridDim.x, k);
+    const int tile = batch_tile(b, b.total_site_tiles, blockIdx.x, gridDim.x, k);
     if (tile == -1) break;
     if (tile < 0) continue;
-    const BatchEntry& e = b.e[find_lattice(b, tile)];
+    const BatchEntry& e = b.e[find_lattice<true>(b, tile)];
     const Geom g = geom_of(e);
-    const int local = tile - e.tile_begin;
-    const int cb = (local >> 3) * kBlock + threadIdx.x;
-    if (cb < g.Vh) staples_link(g, static_cast<const T*>(e.U), static_cast<T*>(e.S8), local & 3, (local >> 2) & 1, cb);
+    const int local = tile - e.site_tile_begin;
+    const int cb = (local >> 1) * kBlock + threadIdx.x;
+    if (cb < g.Vh) staples_site(g, static_cast<const T*>(e.U), static_cast<T*>(e.S8), local & 1, cb);
   }
 }
 
@@ -60,10 +64,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void force_batch_kernel(const BatchTable b, double* __restrict__ partials,
                                                              Coeffs cf) {
   for (int k = 0;; ++k) {
-    const int tile = batch_tile(b, blockIdx.x, gridDim.x, k);
+    const int tile = batch_tile(b, b.total_tiles, blockIdx.x, gridDim.x, k);
     if (tile == -1) break;
     if (tile < 0) continue;
-    const BatchEntry& e = b.e[find_lattice(b, tile)];
+    const BatchEntry& e = b.e[find_lattice<false>(b, tile)];
     const Geom g = geom_of(e);
     const int local = tile - e.tile_begin;
     const int cb = (local >> 3) * kBlock + threadIdx.x;
@@ -105,7 +109,10 @@ __global__ __launch_bounds__(256) void finish_batch_kernel(const BatchTable b, c
 
 template <typename T>
 hipError_t launch_staples_batch(const BatchTable& b, int grid, hipStream_t s) {
-  staples_batch_kernel<T><<<grid, kBlock, 0, s>>>(b);
+  // the persistent grid of the force pass covers every site tile; one workgroup per site
+  // tile otherwise
+  const int g = grid > 0 ? grid : (b.order == 1 ? (b.total_site_tiles + 7) / 8 * 8 : b.total_site_tiles);
+  staples_batch_kernel<T><<<g, kBlock, 0, s>>>(b);
   return hipGetLastError();
 }
 

@@ -6,14 +6,14 @@ namespace sym {
 namespace {
 
 using factored::factored_link;
-using factored::staples_link;
+using factored::staples_site;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void staples_kernel(Geom g, const T* __restrict__ U, T* __restrict__ S8,
                                                          int ntiles) {
-  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
-  const int cb = lt.chunk * kBlock + threadIdx.x;
-  if (cb < g.Vh) staples_link(g, U, S8, lt.mu, lt.p, cb);
+  const SiteTile st = site_tile(g, blockIdx.x, ntiles);
+  const int cb = st.chunk * kBlock + threadIdx.x;
+  if (cb < g.Vh) staples_site(g, U, S8, st.p, cb);
 }
 
 template <typename T, ForceOut MODE>
@@ -32,12 +32,8 @@ __global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T*
 
 template <typename T>
 hipError_t launch_staples(const Geom& g, const T* U, T* S8, hipStream_t s) {
-  const int nt = link_tiles(g);
-  // FP64: two workgroups per CU (by a 56 KiB LDS reservation; 5 by registers alone) keep
-  // the links in flight within L2: 2.16 -> 1.94 ms on the 32^3 x 64 workload. FP32 is
-  // fastest at full occupancy.
-  const size_t lds = sizeof(T) == 8 ? 56 * 1024 : 0;
-  staples_kernel<T><<<nt, kBlock, lds, s>>>(g, U, S8, nt);
+  const int nt = site_tiles(g);
+  staples_kernel<T><<<nt, kBlock, 0, s>>>(g, U, S8, nt);
   return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ enum class ForceOut { Store = 0, Kick = 1, Grad = 2 };
 
 // Number of workgroups of a per-link launch (a multiple of 8: 4 directions x 2 parities).
 inline int link_tiles(const Geom& g) { return ((g.Vh + kBlock - 1) / kBlock) * 8; }
+// Number of workgroups of a per-site launch (2 parities per chunk, rounded up to a
+// multiple of 8 for the XCD-contiguous order).
+inline int site_tiles(const Geom& g) { return (((g.Vh + kBlock - 1) / kBlock) * 2 + 7) & ~7; }
 
 // Each per-link force launch writes 3 doubles per workgroup: sum of Re tr(U t_X).
 // The action kernel writes 3 per workgroup too (W_X partials).
@@ -32,8 +35,8 @@ template <typename T>
 hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, double* partials,
                                const Coeffs& c, ForceOut mode, hipStream_t s);
 
-// Factored force: plaquette staples first (one pass), then rectangles and cube loops
-// assembled from them (second pass).
+// Factored force: plaquette staples first (one pass, one thread per site), then
+// rectangles and cube loops assembled from them (second pass, one thread per link).
 // Staple buffer: 8 slots of 6 complex (two rows) per link (two slots unused), see
 // force_factored.hip.
 // Its element planes are kS8Pad complex numbers longer than V/2 so that the 576 planes
@@ -55,10 +58,11 @@ hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out,
 
 // Batched factored force over many independent lattices (force_batch.hip). The work
 // table travels by value in the kernel arguments, so a captured launch holds no host
-// pointers. Tiles of all lattices are concatenated (tile_begin ascending); persistent
-// workgroups walk them with a static schedule:
+// pointers. Tiles of all lattices are concatenated (tile_begin / site_tile_begin
+// ascending); persistent workgroups walk them with a static schedule:
 //   order 0: tile = blockIdx + k * grid;
 //   order 1: XCD x (= blockIdx % 8) owns the x-th eighth of the tiles, walked in order.
+// launch_staples_batch: grid 0 means one workgroup per site tile.
 constexpr int kMaxBatch = 64;
 struct BatchEntry {
   const void* U;
@@ -66,13 +70,15 @@ struct BatchEntry {
   void* S8;
   int L[4];
   int Vh;
-  int tile_begin;
+  int tile_begin;       // first link tile of the lattice (force pass)
+  int site_tile_begin;  // first site tile of the lattice (staple pass)
+  int pad;
 };
 struct BatchTable {
   int n;
-  int total_tiles;
+  int total_tiles;       // link tiles of all lattices
+  int total_site_tiles;  // site tiles of all lattices
   int order;
-  int pad;
   BatchEntry e[kMaxBatch];
 };
 template <typename T>

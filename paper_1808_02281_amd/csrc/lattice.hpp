@@ -225,6 +225,28 @@ __device__ __forceinline__ LinkTile link_tile(const Geom& g, int linear, int nti
   return r;
 }
 
+// Per-site kernels (one thread per site of one parity): workgroup -> (parity,
+// 256-site chunk), the two parities of a chunk adjacent, with the same XCD slabs and
+// t-fastest walk as link_tile. ntiles is a multiple of 8; tiles past the lattice give
+// chunks whose sites lie beyond V/2 (the kernels skip them).
+struct SiteTile {
+  int p, chunk;
+};
+
+__device__ __forceinline__ SiteTile site_tile(const Geom& g, int linear, int ntiles) {
+  const int tile = xcd_tile(linear, ntiles);
+  SiteTile r;
+  r.p = tile & 1;
+  int chunk = tile >> 1;
+  if (g.tslab > 0) {
+    const int per = ntiles >> 4;  // chunks per XCD = tslab * cps
+    const int xcd = chunk / per, j = chunk - xcd * per;
+    chunk = (xcd * g.tslab + j % g.tslab) * g.cps + j / g.tslab;
+  }
+  r.chunk = chunk;
+  return r;
+}
+
 // ------------------------------------------------------------ FP64 reductions
 // Fixed-order (deterministic) sums: wavefront butterfly, then the block's waves in
 // order. No atomics.
