@@ -26,14 +26,15 @@ sys.path.insert(0, ROOT)
 METRIC = "link-forces/sec + % HBM/VALU roofline, Symanzik force 32^3x64, FP32 vs FP64"
 WORKLOAD = "thermal_32x32x32x64"
 
-# Work per link-force (flop; FMA = 2). See the design notes for the derivation.
+# Work per link-force (flop; FMA = 2; SU(3) product 198, product accumulated into a
+# matrix 216). See the design notes for the derivation.
 FLOP_PAPER = 36770          # the paper's algorithm: 180 staple products, sums, U t, TA
-FLOP_STAPLES = 2376         # factored pass 1: 6 plaquette staples x 2 products
-FLOP_FACTORED = 11494       # factored pass 2: 51 products + sums, traces, TA
+FLOP_STAPLES = 2079         # factored pass 1: 42 products per site (10.5 per link)
+FLOP_FACTORED = 12909       # factored pass 2: 57 products, 55 accumulations, weights, traces, TA
 FLOP_DIRECT = 36940         # direct kernel: 181 products + sums, traces, TA
 # Minimum HBM bytes per link of each kernel (read once / write once), per real size r.
 BYTES_STAPLES = lambda r: (12 + 6 * 12) * r              # read U (two rows), write 6 two-row staples
-BYTES_FACTORED = lambda r: (18 + 6 * 12 + 18) * r        # read U and own staples, write G
+BYTES_FACTORED = lambda r: (12 + 6 * 12 + 18) * r        # read U (two rows) and own staples, write G
 BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 
 # Fat-link path force (asqtad/HISQ smearing), flop per link of each kernel, counted from

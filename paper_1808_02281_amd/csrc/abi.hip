@@ -73,10 +73,12 @@ int make_coeffs(double u0, double beta, Coeffs* c) {
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // Workspace regions: [A: per-workgroup action partials, 3 doubles each]
-// [B: per-workgroup kinetic partials] [C: plaquette staples, 8 slots of two rows per link].
+// [B: per-workgroup kinetic partials, then the stage of the final reduction]
+// [C: plaquette staples, 8 slots of two rows per link].
 struct Workspace {
   double* act;
   double* kin;
+  double* stage;
   void* staples;
 };
 
@@ -84,7 +86,9 @@ size_t region_a(const Geom& g) {
   const int n = sym::link_tiles(g) > sym::action_tiles(g) ? sym::link_tiles(g) : sym::action_tiles(g);
   return align256(sizeof(double) * 3 * (size_t)n);
 }
-size_t region_b(const Geom& g) { return align256(sizeof(double) * (size_t)sym::link_tiles(g)); }
+size_t region_b(const Geom& g) {
+  return align256(sizeof(double) * ((size_t)sym::link_tiles(g) + sym::kFinishStage));
+}
 size_t region_c(const Geom& g, int prec) {
   const size_t real = prec == SYM_F64 ? sizeof(double) : sizeof(float);
   return align256((size_t)8 * sym::s8_stride(g) * 8 * 12 * real);  // 8 staple slots of 2 rows per link
@@ -97,6 +101,7 @@ Workspace carve(void* ws, const Geom& g) {
   Workspace w;
   w.act = reinterpret_cast<double*>(p);
   w.kin = reinterpret_cast<double*>(p + region_a(g));
+  w.stage = w.kin + sym::link_tiles(g);
   w.staples = p + region_a(g) + region_b(g);
   return w;
 }
@@ -234,7 +239,7 @@ template <typename T>
 hipError_t action_into(const Geom& g, const Coeffs& c, const T* U, double* S_dev, const Workspace& w, hipStream_t s) {
   hipError_t e = timed("action", s, [&] { return sym::launch_action<T>(g, U, w.act, s); });
   if (e == hipSuccess)
-    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, sym::action_tiles(g), 1, g, c, S_dev, s); });
+    e = timed("finish", s, [&] { return sym::launch_finish_action(w.act, sym::action_tiles(g), 1, g, c, w.stage, S_dev, s); });
   return e;
 }
 
@@ -248,7 +253,8 @@ int do_force(bool factored, const Geom& g, const Coeffs& c, const void* Uv, void
   hipError_t e = force_into<T>(factored, g, U, static_cast<T*>(out), 0.0, fused ? w.act : nullptr, c, mode, w, s);
   if (e == hipSuccess && fused)
     e = timed("finish", s, [&] {
-      return sym::launch_finish_action(w.act, force_tiles(factored, g), force_kind(factored), g, c, S_dev, s);
+      return sym::launch_finish_action(w.act, force_tiles(factored, g), force_kind(factored), g, c, w.stage, S_dev,
+                                       s);
     });
   else if (e == hipSuccess && S_dev)
     e = action_into<T>(g, c, U, S_dev, w, s);
@@ -267,7 +273,8 @@ hipError_t hamiltonian(const Geom& g, const Coeffs& c, const T* U, const T* P, d
   if (e == hipSuccess) e = timed("kinetic", s, [&] { return sym::launch_kinetic<T>(g, P, w.kin, s); });
   if (e == hipSuccess)
     e = timed("finish", s, [&] {
-      return sym::launch_finish_hamiltonian(w.act, sym::action_tiles(g), 1, w.kin, sym::link_tiles(g), g, c, out, s);
+      return sym::launch_finish_hamiltonian(w.act, sym::action_tiles(g), 1, w.kin, sym::link_tiles(g), g, c, w.stage,
+                                            out, s);
     });
   return e;
 }
@@ -289,7 +296,7 @@ int do_leapfrog(bool factored, const Geom& g, const Coeffs& c, void* Uv, void* P
   auto finish_h = [&](double* out) {
     return timed("finish", s, [&] {
       return sym::launch_finish_hamiltonian(w.act, force_tiles(factored, g), force_kind(factored), w.kin,
-                                            sym::link_tiles(g), g, c, out, s);
+                                            sym::link_tiles(g), g, c, w.stage, out, s);
     });
   };
   double* act = H_dev ? w.act : nullptr;
@@ -315,6 +322,7 @@ struct BatchPlan {
   std::vector<Geom> g;
   std::vector<size_t> s8_off;
   size_t part_bytes = 0;
+  size_t stage_off = 0;  // doubles from the start of the partials region
   size_t total = 0;
 };
 
@@ -335,7 +343,9 @@ int batch_plan(int n, const int32_t* L, int prec, BatchPlan* plan) {
     if (tiles > (1ll << 30)) return SYM_EINVAL;
     max_chunk_tiles = tiles > max_chunk_tiles ? tiles : max_chunk_tiles;
   }
-  plan->part_bytes = align256(sizeof(double) * 3 * (size_t)max_chunk_tiles);
+  // per-tile partials, then the stage of the final reduction (c_C = 0 only)
+  plan->stage_off = 3 * (size_t)max_chunk_tiles;
+  plan->part_bytes = align256(sizeof(double) * (3 * (size_t)max_chunk_tiles + sym::kFinishStage));
   size_t off = plan->part_bytes;
   for (int i = 0; i < n; ++i) {
     plan->s8_off[i] = off;
@@ -404,7 +414,7 @@ hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const 
   // kernel of each lattice supplies S and W, its partials in the batch partials region
   // (a lattice has fewer action tiles than link tiles)
   for (int i = 0; i < n && e == hipSuccess && S_dev && c.c[2] == 0.0; ++i) {
-    Workspace w{parts, nullptr, nullptr};
+    Workspace w{parts, nullptr, parts + plan.stage_off, nullptr};
     e = action_into<T>(plan.g[i], c, static_cast<const T*>(U[i]), S_dev + 4 * i, w, s);
   }
   return e;

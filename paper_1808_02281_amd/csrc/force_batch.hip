@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256) void finish_batch_kernel(const BatchTable b, c
   const int t0 = b.e[l].tile_begin;
   const int t1 = l + 1 < b.n ? b.e[l + 1].tile_begin : b.total_tiles;
   double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
     v[0] += partials[3 * (size_t)t + 0];
     v[1] += partials[3 * (size_t)t + 1];

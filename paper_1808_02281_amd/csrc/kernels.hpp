@@ -101,16 +101,18 @@ hipError_t launch_action(const Geom& g, const T* U, double* partials, hipStream_
 //   kind 2 (factored force): plaquette / long-side rectangle / (c_R short-side
 //          rectangle + c_C cube) sums, see force_factored.hip.
 // launch_finish_action writes out[0..3] = S, W_P, W_R, W_C; launch_finish_hamiltonian
-// adds the kinetic partials and writes out[0] = S + kinetic.
+// adds the kinetic partials and writes out[0] = S + kinetic. Both reduce in two fixed-
+// order stages through `stage` (kFinishStage doubles of workspace).
+constexpr int kFinishStage = 4 * 64;
 hipError_t launch_finish_action(const double* partials, int nparts, int kind, const Geom& g,
-                                const Coeffs& c, double* out, hipStream_t s);
+                                const Coeffs& c, double* stage, double* out, hipStream_t s);
 
 // Leapfrog pieces.
 template <typename T>
 hipError_t launch_kinetic(const Geom& g, const T* P, double* partials, hipStream_t s);
 hipError_t launch_finish_hamiltonian(const double* act_parts, int nact, int act_kind,
                                      const double* kin_parts, int nkin, const Geom& g,
-                                     const Coeffs& c, double* out, hipStream_t s);
+                                     const Coeffs& c, double* stage, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_drift(const Geom& g, T* U, const T* P, double dt, hipStream_t s);
 
