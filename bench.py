@@ -187,9 +187,10 @@ def bench_batch(sym, torch, gaugegen, u0, beta, reps=20):
     out["per_lattice_graph"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3)}
     ms = timed(batched)
     out["batched_default"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "launches": 3}
-    grid, order = sym.batch_autotune(Us, Ls, u0, beta)
+    best, tune_log = sym.batch_autotune(Us, Ls, u0, beta)
     ms = timed(batched)
-    out["batched_tuned"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "grid": grid, "order": order}
+    out["batched_tuned"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3), "schedule": best}
+    out["autotune_log"] = [{**c, "ms": t} for c, t in tune_log]
     ms = graphed(batched)
     out["batched_tuned_graph"] = {"ms": ms, "link_forces_per_s": links / (ms * 1e-3)}
     return out

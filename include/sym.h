@@ -156,25 +156,34 @@ int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, v
  * workspace) and replayed. L: host array of n x 4 dims. U, F: host arrays of n device
  * pointers (fields as in sym_force). S_dev: NULL or 4n device doubles, {S, W_P, W_R, W_C}
  * per lattice. ws: at least sym_batch_workspace_bytes(n, L, prec) bytes (0 if invalid).
- * The schedule (number of persistent workgroups, or one workgroup per tile; tile
- * order) is the one sym_batch_autotune chose for these shapes and precision in this
- * process, else one workgroup per tile in an XCD-contiguous order.
+ * The schedule (number of persistent workgroups, or one workgroup per tile; tile order;
+ * links per workgroup; occupancy cap) is the one sym_batch_autotune chose for these
+ * shapes and precision in this process, else one workgroup of 256 links per tile in an
+ * XCD-contiguous order at the occupancy of sym_force. Every schedule gives the same
+ * forces; the actions agree to rounding (the partial sums are grouped by workgroup).
  */
 size_t sym_batch_workspace_bytes(int n, const int32_t* L, int prec);
 int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
                     double* S_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
 
 /*
- * Autotuner for sym_force_batch: times every candidate schedule (256..4096 persistent
- * workgroups, or one workgroup per tile, reported as grid 0; x two tile orders) on the
- * caller's fields (F is overwritten: it ends with the forces of the last schedule
- * timed, 256 persistent workgroups in XCD-contiguous order), synchronising the stream,
- * keeps the fastest for later calls with the same shapes and precision (in-process
- * cache), and returns it through grid_out / order_out (nullable). Not for use under
- * graph capture.
+ * Autotuner for sym_force_batch: times (mean of 3 runs after a warm-up) every candidate
+ * schedule of the force pass, 48 in all:
+ *   links per workgroup {256, 128} x LDS reserved per workgroup {0, the sym_force default,
+ *   96 KiB (one workgroup per CU)}, which caps the resident waves per SIMD, x grid {one
+ *   workgroup per tile (reported as 0), 2048, 1024, 512 persistent workgroups} x tile
+ *   order {strided, XCD-contiguous},
+ * on the caller's fields (F is overwritten: it ends with the forces of the last schedule
+ * timed), synchronising the stream, keeps the fastest for later sym_force_batch calls with
+ * the same shapes and precision (in-process cache), and writes it to schedule_out
+ * (nullable; 4 ints: grid, order, links per workgroup, LDS KiB with -1 = default). The
+ * first max_log candidates are logged: log_schedules (nullable, 4 ints each, as
+ * schedule_out) and log_ms (nullable, milliseconds per batch); n_log_out (nullable)
+ * receives their number. SYM_EINVAL if max_log < 0. Not for use under graph capture.
  */
 int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
-                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out);
+                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* schedule_out, int32_t max_log,
+                       int32_t* log_schedules, float* log_ms, int32_t* n_log_out);
 
 /*
  * Fat-link smearing of the asqtad and HISQ actions and the force it induces on the thin

@@ -103,7 +103,8 @@ def lib():
                                   ctypes.c_size_t, vp]
     L.sym_force_batch.restype = ctypes.c_int
     L.sym_batch_autotune.argtypes = [ctypes.c_int, i32p, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp, vp,
-                                     ctypes.c_size_t, vp, i32p, i32p]
+                                     ctypes.c_size_t, vp, i32p, ctypes.c_int32, i32p, ctypes.POINTER(ctypes.c_float),
+                                     i32p]
     L.sym_batch_autotune.restype = ctypes.c_int
     L.sym_fat_workspace_bytes.argtypes = [i32p, ctypes.c_int]
     L.sym_fat_workspace_bytes.restype = ctypes.c_size_t

@@ -255,10 +255,12 @@ def force_batch(Us, Ls, u0, beta, with_action=False, out=None, S_out=None):
 
 
 def batch_autotune(Us, Ls, u0, beta, out=None):
-    """Time the candidate schedules of force_batch for this batch; the best one is kept
-    for later force_batch calls with the same lattice shapes. Returns (grid, order);
-    grid 0 is one workgroup per tile. ``out`` (optional, one field per lattice) receives
-    the forces of the last schedule timed (256 persistent workgroups)."""
+    """Time the candidate schedules of force_batch for this batch (sym_batch_autotune);
+    the best one is kept for later force_batch calls with the same lattice shapes.
+    Returns (best, log): best = {grid, order, links, lds_kib} (grid 0 is one workgroup per
+    tile, lds_kib -1 the default occupancy), log = [(schedule dict, ms per batch), ...]
+    for every candidate. ``out`` (optional, one field per lattice) receives the forces of
+    the last schedule timed."""
     n, Lflat, prec = _batch_args(Us, Ls)
     dev = Us[0].device
     ws = batch_workspace(Ls, prec, dev)
@@ -270,11 +272,18 @@ def batch_autotune(Us, Ls, u0, beta, out=None):
             raise ValueError("out fields must match U in shape and dtype and be contiguous")
     Up = (ctypes.c_void_p * n)(*[U.data_ptr() for U in Us])
     Fp = (ctypes.c_void_p * n)(*[F.data_ptr() for F in Fs])
-    grid, order = ctypes.c_int32(), ctypes.c_int32()
+    best = (ctypes.c_int32 * 4)()
+    nmax = 256
+    sched = (ctypes.c_int32 * (4 * nmax))()
+    ms = (ctypes.c_float * nmax)()
+    nlog = ctypes.c_int32()
     _lib.check("sym_batch_autotune", _lib.lib().sym_batch_autotune(n, Lflat, float(u0), float(beta), prec, Up, Fp,
-                                                                   _ptr(ws), ws.numel(), _stream(dev),
-                                                                   ctypes.byref(grid), ctypes.byref(order)))
-    return grid.value, order.value
+                                                                   _ptr(ws), ws.numel(), _stream(dev), best, nmax,
+                                                                   sched, ms, ctypes.byref(nlog)))
+    keys = ("grid", "order", "links", "lds_kib")
+    as_dict = lambda v: {k: int(x) for k, x in zip(keys, v)}
+    log = [(as_dict(sched[4 * i: 4 * i + 4]), float(ms[i])) for i in range(nlog.value)]
+    return as_dict(best[:]), log
 
 
 # ------------------------------------------------------------------ fat links

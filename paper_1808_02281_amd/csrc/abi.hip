@@ -316,8 +316,10 @@ int do_leapfrog(bool factored, const Geom& g, const Coeffs& c, void* Uv, void* P
 }
 
 // ------------------------------------------------------------ batched force
-// Workspace: [partials: 3 doubles per tile of the largest launch chunk]
+// Workspace: [partials: 3 doubles per tile of the largest launch chunk, counted with the
+//             smallest workgroup any schedule uses]
 //            [per lattice: plaquette-staple buffer, 256-byte aligned]
+constexpr int kMinBatchLinks = 128;
 struct BatchPlan {
   std::vector<Geom> g;
   std::vector<size_t> s8_off;
@@ -338,7 +340,7 @@ int batch_plan(int n, const int32_t* L, int prec, BatchPlan* plan) {
     long long tiles = 0;
     for (int i = c0; i < n && i < c0 + sym::kMaxBatch; ++i) {
       if ((rc = make_geom(L + 4 * i, &plan->g[i])) != SYM_OK) return rc;
-      tiles += sym::link_tiles(plan->g[i]);
+      tiles += sym::link_tiles(plan->g[i], kMinBatchLinks);  // the most tiles any schedule uses
     }
     if (tiles > (1ll << 30)) return SYM_EINVAL;
     max_chunk_tiles = tiles > max_chunk_tiles ? tiles : max_chunk_tiles;
@@ -355,11 +357,18 @@ int batch_plan(int n, const int32_t* L, int prec, BatchPlan* plan) {
   return SYM_OK;
 }
 
-// grid: number of persistent workgroups, or 0 for one workgroup per tile (the launch
-// covers every tile of its lattices and the hardware dispatcher balances them)
+// Schedule of the batched force pass.
+//   grid: number of persistent workgroups, or 0 for one workgroup per tile (the launch
+//         covers every tile of its lattices and the hardware dispatcher balances them);
+//   order: tile order (0 strided, 1 XCD-contiguous, see BatchTable);
+//   links: links (threads) per workgroup, 256 or 128;
+//   lds_kib: dynamic LDS reserved per workgroup, capping the workgroups per CU (160 KiB
+//            of LDS) and hence the waves per SIMD; -1 = the single-lattice default.
 struct Schedule {
   int grid;
   int order;
+  int links;
+  int lds_kib;
 };
 std::mutex g_tune_mu;
 std::map<std::vector<int>, Schedule> g_tune;
@@ -371,10 +380,10 @@ std::vector<int> tune_key(int n, const int32_t* L, int prec) {
 }
 
 Schedule default_schedule(int) {
-  // one workgroup per tile, XCD-contiguous: on 64 lattices from {8^4, 12^4, 16^3x32}
-  // (FP32) 4.93 ms, against 6.59 ms for one round of persistent workgroups (512) and
-  // 5.82 ms for 64 single-lattice calls
-  return Schedule{0, 1};
+  // one workgroup of 256 links per tile, XCD-contiguous, the single-lattice occupancy:
+  // on 64 lattices from {8^4, 12^4, 16^3x32} (FP32) 4.43 ms, against 5.41 ms for 64
+  // single-lattice calls
+  return Schedule{0, 1, 256, -1};
 }
 
 template <typename T>
@@ -399,14 +408,16 @@ hipError_t force_batch_run(int n, const BatchPlan& plan, const Coeffs& c, const 
       en.Vh = plan.g[i].Vh;
       en.tile_begin = tiles;
       en.site_tile_begin = site_tiles;
-      tiles += sym::link_tiles(plan.g[i]);
+      tiles += sym::link_tiles(plan.g[i], sch.links);
       site_tiles += sym::site_tiles(plan.g[i]);
     }
     b.total_tiles = tiles;
     b.total_site_tiles = site_tiles;
     const int grid = sch.grid > 0 ? sch.grid : (sch.order == 1 ? (tiles + 7) / 8 * 8 : tiles);
     e = timed("staples_batch", s, [&] { return sym::launch_staples_batch<T>(b, sch.grid, s); });
-    if (e == hipSuccess) e = timed("force_batch", s, [&] { return sym::launch_force_batch<T>(b, grid, parts, c, s); });
+    if (e == hipSuccess)
+      e = timed("force_batch", s,
+                [&] { return sym::launch_force_batch<T>(b, grid, sch.links, sch.lds_kib, parts, c, s); });
     if (e == hipSuccess && S_dev && c.c[2] != 0.0)
       e = timed("finish_batch", s, [&] { return sym::launch_finish_batch(b, parts, c, S_dev + 4 * c0, s); });
   }
@@ -543,43 +554,67 @@ int sym_force_batch(int n, const int32_t* L, double u0, double beta, int prec, c
 }
 
 int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec, const void* const* U, void* const* F,
-                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* grid_out, int32_t* order_out) {
+                       void* ws, size_t ws_bytes, sym_stream_t stream, int32_t* schedule_out, int32_t max_log,
+                       int32_t* log_schedules, float* log_ms, int32_t* n_log_out) {
   BatchPlan plan;
   Coeffs c;
   int rc;
   if ((rc = batch_plan(n, L, prec, &plan)) || (rc = make_coeffs(u0, beta, &c)) || (rc = check_batch_ptrs(n, U, F)) ||
       (rc = check_ptr(ws)))
     return rc;
+  if (max_log < 0) return SYM_EINVAL;
   if (ws_bytes < plan.total) return SYM_EWORKSPACE;
   if ((rc = check_batch_disjoint(n, plan, prec, U, F, nullptr, ws))) return rc;
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return SYM_EHIP;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return SYM_EHIP;
+  }
   Schedule best = default_schedule(prec);
   float best_ms = -1.0f;
-  // the last candidate timed is 256 persistent workgroups in XCD-contiguous order
-  const int grids[] = {0, 4096, 3072, 2048, 1536, 1024, 768, 512, 256};
+  int nlog = 0;
+  // links per workgroup x occupancy cap (LDS KiB per workgroup: none, the default, one
+  // workgroup per CU) x grid (one workgroup per tile, or persistent) x tile order; the
+  // last candidate timed is 512 persistent workgroups of 128 links in XCD-contiguous order
+  // with one workgroup per CU
+  const int linkss[] = {256, 128};
+  const int ldss[] = {0, -1, 96};
+  const int grids[] = {0, 2048, 1024, 512};
   hipError_t e = hipSuccess;
-  for (int order = 0; order < 2 && e == hipSuccess; ++order)
-    for (int grid : grids) {
-      const Schedule sch{grid, order};
-      auto run = [&] {
-        return prec == SYM_F64 ? force_batch_run<double>(n, plan, c, U, F, nullptr, ws, sch, s)
-                               : force_batch_run<float>(n, plan, c, U, F, nullptr, ws, sch, s);
-      };
-      if ((e = run()) != hipSuccess) break;  // warm-up
-      if ((e = hipEventRecord(a, s)) != hipSuccess) break;
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
-      if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      if (e != hipSuccess) break;
-      if (best_ms < 0.0f || ms < best_ms) {
-        best_ms = ms;
-        best = sch;
-      }
-    }
+  for (int li = 0; li < 2 && e == hipSuccess; ++li)
+    for (int lds : ldss)
+      for (int grid : grids)
+        for (int order = 0; order < 2 && e == hipSuccess; ++order) {
+          const Schedule sch{grid, order, linkss[li], lds};
+          auto run = [&] {
+            return prec == SYM_F64 ? force_batch_run<double>(n, plan, c, U, F, nullptr, ws, sch, s)
+                                   : force_batch_run<float>(n, plan, c, U, F, nullptr, ws, sch, s);
+          };
+          if ((e = run()) != hipSuccess) break;  // warm-up
+          if ((e = hipEventRecord(a, s)) != hipSuccess) break;
+          for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+          if (e == hipSuccess) e = hipEventRecord(b, s);
+          if (e == hipSuccess) e = hipEventSynchronize(b);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+          if (e != hipSuccess) break;
+          ms /= 3.0f;
+          if (nlog < max_log) {
+            if (log_schedules) {
+              log_schedules[4 * nlog + 0] = sch.grid;
+              log_schedules[4 * nlog + 1] = sch.order;
+              log_schedules[4 * nlog + 2] = sch.links;
+              log_schedules[4 * nlog + 3] = sch.lds_kib;
+            }
+            if (log_ms) log_ms[nlog] = ms;
+            ++nlog;
+          }
+          if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = sch;
+          }
+        }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return SYM_EHIP;
@@ -587,8 +622,13 @@ int sym_batch_autotune(int n, const int32_t* L, double u0, double beta, int prec
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(n, L, prec)] = best;
   }
-  if (grid_out) *grid_out = best.grid;
-  if (order_out) *order_out = best.order;
+  if (schedule_out) {
+    schedule_out[0] = best.grid;
+    schedule_out[1] = best.order;
+    schedule_out[2] = best.links;
+    schedule_out[3] = best.lds_kib;
+  }
+  if (n_log_out) *n_log_out = nlog;
   return SYM_OK;
 }
 

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void force_batch_kernel(const BatchTable b,
     const BatchEntry& e = b.e[find_lattice<false>(b, tile)];
     const Geom g = geom_of(e);
     const int local = tile - e.tile_begin;
-    const int cb = (local >> 3) * kBlock + threadIdx.x;
+    const int cb = (local >> 3) * (int)blockDim.x + threadIdx.x;  // blockDim.x links per tile
     double a[3] = {0.0, 0.0, 0.0};
     if (cb < g.Vh)
       factored_link<T, ForceOut::Store>(g, static_cast<const T*>(e.U), static_cast<const T*>(e.S8),
@@ -118,18 +118,21 @@ hipError_t launch_staples_batch(const BatchTable& b, int grid, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_force_batch(const BatchTable& b, int grid, double* partials, const Coeffs& c, hipStream_t s) {
-  force_batch_kernel<T><<<grid, kBlock, factored_lds_reservation<T>(), s>>>(b, partials, c);
+hipError_t launch_force_batch(const BatchTable& b, int grid, int links, int lds_kib, double* partials,
+                              const Coeffs& c, hipStream_t s) {
+  const size_t lds = lds_kib < 0 ? factored_lds_reservation<T>() : (size_t)lds_kib * 1024;
+  force_batch_kernel<T><<<grid, links, lds, s>>>(b, partials, c);
   return hipGetLastError();
 }
 
 #ifndef SYM_ONLY_F64
 template hipError_t launch_staples_batch<float>(const BatchTable&, int, hipStream_t);
-template hipError_t launch_force_batch<float>(const BatchTable&, int, double*, const Coeffs&, hipStream_t);
+template hipError_t launch_force_batch<float>(const BatchTable&, int, int, int, double*, const Coeffs&, hipStream_t);
 #endif
 #ifndef SYM_ONLY_F32
 template hipError_t launch_staples_batch<double>(const BatchTable&, int, hipStream_t);
-template hipError_t launch_force_batch<double>(const BatchTable&, int, double*, const Coeffs&, hipStream_t);
+template hipError_t launch_force_batch<double>(const BatchTable&, int, int, int, double*, const Coeffs&,
+                                               hipStream_t);
 // the finish kernel is precision independent; it lives in the FP64 object
 hipError_t launch_finish_batch(const BatchTable& b, const double* partials, const Coeffs& c, double* out,
                                hipStream_t s) {

@@ -21,8 +21,9 @@ struct Coeffs {
 // tangent space of SU(3) at U, 2 G U (see sym_action_grad).
 enum class ForceOut { Store = 0, Kick = 1, Grad = 2 };
 
-// Number of workgroups of a per-link launch (a multiple of 8: 4 directions x 2 parities).
-inline int link_tiles(const Geom& g) { return ((g.Vh + kBlock - 1) / kBlock) * 8; }
+// Number of workgroups of a per-link launch (a multiple of 8: 4 directions x 2 parities)
+// with `links` links (threads) per workgroup.
+inline int link_tiles(const Geom& g, int links = kBlock) { return ((g.Vh + links - 1) / links) * 8; }
 // Number of workgroups of a per-site launch (2 parities per chunk, rounded up to a
 // multiple of 8 for the XCD-contiguous order).
 inline int site_tiles(const Geom& g) { return (((g.Vh + kBlock - 1) / kBlock) * 2 + 7) & ~7; }
@@ -84,7 +85,11 @@ struct BatchTable {
 template <typename T>
 hipError_t launch_staples_batch(const BatchTable& b, int grid, hipStream_t s);
 template <typename T>
-hipError_t launch_force_batch(const BatchTable& b, int grid, double* partials, const Coeffs& c, hipStream_t s);
+// links: threads (links) per workgroup of the force pass, 256 or 128 (the table's link
+// tiles must have been counted with it); lds_kib: dynamic LDS reserved per workgroup, which
+// caps the resident workgroups per CU (negative: the single-lattice default).
+hipError_t launch_force_batch(const BatchTable& b, int grid, int links, int lds_kib, double* partials,
+                              const Coeffs& c, hipStream_t s);
 // One block per lattice: per-lattice action from the pass-2 partials (kind 2).
 hipError_t launch_finish_batch(const BatchTable& b, const double* partials, const Coeffs& c, double* out,
                                hipStream_t s);

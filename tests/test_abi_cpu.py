@@ -240,16 +240,17 @@ def test_batch_validation(L_):
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, outs, None, None, HUGE, None) == -2
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, outs, None, WS, 64, None) == -3
     at = L_.sym_batch_autotune
-    assert at(0, two, 0.8677, 3.0, 1, ptrs, outs, WS, HUGE, None, None, None) == -1
-    assert at(2, two, 0.8677, 3.0, 2, holes, outs, WS, HUGE, None, None, None) == -2
-    assert at(2, two, 0.8677, 3.0, 1, ptrs, outs, WS, 64, None, None, None) == -3
+    assert at(0, two, 0.8677, 3.0, 1, ptrs, outs, WS, HUGE, None, None, 0, None, None, None) == -1
+    assert at(2, two, 0.8677, 3.0, 2, holes, outs, WS, HUGE, None, None, 0, None, None, None) == -2
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, outs, WS, 64, None, None, 0, None, None, None) == -3
     # an output aliasing an input of another lattice, or two outputs coinciding
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, ptrs, None, WS, HUGE, None) == -1
     crossed = (ctypes.c_void_p * 2)(0x12000000, 0x10000000)
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, crossed, None, WS, HUGE, None) == -1
     same = (ctypes.c_void_p * 2)(0x12000000, 0x12000000)
     assert fb(2, two, 0.8677, 3.0, 1, ptrs, same, None, WS, HUGE, None) == -1
-    assert at(2, two, 0.8677, 3.0, 1, ptrs, same, WS, HUGE, None, None, None) == -1
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, same, WS, HUGE, None, None, 0, None, None, None) == -1
+    assert at(2, two, 0.8677, 3.0, 1, ptrs, outs, WS, HUGE, None, None, -1, None, None, None) == -1   # max_log
 
 
 def test_static_force_validation(L_):

@@ -69,14 +69,22 @@ def test_batch_larger_than_one_launch(sym):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_autotune_keeps_results(sym, prec):
-    """The default schedule is one workgroup per tile; the autotuner's last candidate is
-    a persistent grid (256 workgroups, each looping over two or three of the 592 tiles):
-    both, and the schedule it keeps, give bitwise the same forces."""
+    """The autotuner times 48 schedules (256 or 128 links per workgroup, three occupancy
+    caps, one workgroup per tile or 2048/1024/512 persistent workgroups, two tile
+    orders); its last candidate is 512 persistent workgroups of 128 links at one
+    workgroup per CU. The default schedule, the last candidate and the schedule it keeps
+    give bitwise the same forces, and every candidate is logged."""
     Us = _fields(SHAPES, prec, seed0=7)
     F0 = sym.force_batch(Us, SHAPES, U0, BETA)
     Fp = [torch.empty_like(U) for U in Us]
-    grid, order = sym.batch_autotune(Us, SHAPES, U0, BETA, out=Fp)
-    assert grid in (0, 256, 512, 768, 1024, 1536, 2048, 3072, 4096) and order in (0, 1)
+    best, log = sym.batch_autotune(Us, SHAPES, U0, BETA, out=Fp)
+    space = {(g, o, l, d) for g in (0, 2048, 1024, 512) for o in (0, 1) for l in (256, 128) for d in (0, -1, 96)}
+    assert len(log) == 48
+    assert {tuple(c.values()) for c, _ in log} == space
+    assert all(ms > 0 for _, ms in log)
+    assert tuple(best.values()) in space
+    assert min(ms for _, ms in log) == [ms for c, ms in log if c == best][0]
+    print(f"  best schedule {best}; default-like {[ms for c, ms in log if c == dict(grid=0, order=1, links=256, lds_kib=-1)]}")
     F1 = sym.force_batch(Us, SHAPES, U0, BETA)
     for a, b, c in zip(F0, F1, Fp):
         assert torch.equal(a, b)
