@@ -83,7 +83,7 @@ struct Workspace {
 };
 
 size_t region_a(const Geom& g) {
-  const int n = sym::link_tiles(g) > sym::action_tiles(g) ? sym::link_tiles(g) : sym::action_tiles(g);
+  const int n = sym::max_force_tiles(g) > sym::action_tiles(g) ? sym::max_force_tiles(g) : sym::action_tiles(g);
   return align256(sizeof(double) * 3 * (size_t)n);
 }
 size_t region_b(const Geom& g) {
@@ -227,7 +227,10 @@ hipError_t force_into(bool factored, const Geom& g, const T* U, T* out, double k
   return timed("force_direct", s, [&] { return sym::launch_force_direct<T>(g, U, out, kick, act, c, mode, s); });
 }
 
-int force_tiles(bool factored, const Geom& g) { return factored ? sym::factored_tiles(g) : sym::link_tiles(g); }
+template <typename T>
+int force_tiles(bool factored, const Geom& g) {
+  return factored ? sym::factored_tiles<T>(g) : sym::link_tiles(g);
+}
 int force_kind(bool factored) { return factored ? 2 : 0; }
 
 // The factored kernels fold the short-side rectangles and the cube loops into one
@@ -253,7 +256,7 @@ int do_force(bool factored, const Geom& g, const Coeffs& c, const void* Uv, void
   hipError_t e = force_into<T>(factored, g, U, static_cast<T*>(out), 0.0, fused ? w.act : nullptr, c, mode, w, s);
   if (e == hipSuccess && fused)
     e = timed("finish", s, [&] {
-      return sym::launch_finish_action(w.act, force_tiles(factored, g), force_kind(factored), g, c, w.stage, S_dev,
+      return sym::launch_finish_action(w.act, force_tiles<T>(factored, g), force_kind(factored), g, c, w.stage, S_dev,
                                        s);
     });
   else if (e == hipSuccess && S_dev)
@@ -295,7 +298,7 @@ int do_leapfrog(bool factored, const Geom& g, const Coeffs& c, void* Uv, void* P
   // first kick and after the last.
   auto finish_h = [&](double* out) {
     return timed("finish", s, [&] {
-      return sym::launch_finish_hamiltonian(w.act, force_tiles(factored, g), force_kind(factored), w.kin,
+      return sym::launch_finish_hamiltonian(w.act, force_tiles<T>(factored, g), force_kind(factored), w.kin,
                                             sym::link_tiles(g), g, c, w.stage, out, s);
     });
   };

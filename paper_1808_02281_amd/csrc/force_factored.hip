@@ -17,12 +17,14 @@ __global__ __launch_bounds__(kBlock) void staples_kernel(Geom g, const T* __rest
 }
 
 template <typename T, ForceOut MODE>
-__global__ __launch_bounds__(kBlock) void force_factored_kernel(Geom g, const T* __restrict__ U,
-                                                                const T* __restrict__ S8, T* __restrict__ out,
-                                                                double kick, double* __restrict__ partials, Coeffs cf,
-                                                                int ntiles) {
-  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
-  const int cb = lt.chunk * kBlock + threadIdx.x;
+__global__ __launch_bounds__(factored_links<T>()) void force_factored_kernel(Geom g, const T* __restrict__ U,
+                                                                             const T* __restrict__ S8,
+                                                                             T* __restrict__ out, double kick,
+                                                                             double* __restrict__ partials, Coeffs cf,
+                                                                             int ntiles) {
+  constexpr int N = factored_links<T>();
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles, kBlock / N);
+  const int cb = lt.chunk * N + threadIdx.x;
   double a[3] = {0.0, 0.0, 0.0};
   if (cb < g.Vh) factored_link<T, MODE>(g, U, S8, out, kick, cf, lt.mu, lt.p, cb, a);
   if (partials != nullptr) block_sum_store<3>(a, partials + 3 * (size_t)blockIdx.x);
@@ -40,18 +42,16 @@ hipError_t launch_staples(const Geom& g, const T* U, T* S8, hipStream_t s) {
 template <typename T>
 hipError_t launch_force_factored(const Geom& g, const T* U, const T* S8, T* out, double kick, double* partials,
                                  const Coeffs& c, ForceOut mode, hipStream_t s) {
-  const int nt = factored_tiles(g);
-  // Occupancy cap through an LDS reservation (the kernel uses none): fewer resident
-  // waves keep more of each wave's staple reads in L2. Measured on the 32^3 x 64
-  // workload: 2 waves per SIMD for FP32, 1 for FP64, which is also where the
-  // software-pipelined forms land by their register counts alone.
-  const size_t lds = factored_lds_reservation<T>();
+  const int nt = factored_tiles<T>(g);
+  constexpr int N = factored_links<T>();
+  // one or two waves per SIMD by registers (FP64, FP32); no LDS reservation: with
+  // workgroups of one or two waves it would only take waves away
   if (mode == ForceOut::Store)
-    force_factored_kernel<T, ForceOut::Store><<<nt, kBlock, lds, s>>>(g, U, S8, out, kick, partials, c, nt);
+    force_factored_kernel<T, ForceOut::Store><<<nt, N, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
   else if (mode == ForceOut::Kick)
-    force_factored_kernel<T, ForceOut::Kick><<<nt, kBlock, lds, s>>>(g, U, S8, out, kick, partials, c, nt);
+    force_factored_kernel<T, ForceOut::Kick><<<nt, N, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
   else
-    force_factored_kernel<T, ForceOut::Grad><<<nt, kBlock, lds, s>>>(g, U, S8, out, kick, partials, c, nt);
+    force_factored_kernel<T, ForceOut::Grad><<<nt, N, 0, s>>>(g, U, S8, out, kick, partials, c, nt);
   return hipGetLastError();
 }
 

@@ -210,16 +210,18 @@ struct LinkTile {
   int mu, p, chunk;
 };
 
-__device__ __forceinline__ LinkTile link_tile(const Geom& g, int linear, int ntiles) {
+// split: the number of chunks of the launch's workgroup size per 256-site chunk (1, 2 or
+// 4 for 256, 128 or 64 links per workgroup); g.cps counts 256-site chunks.
+__device__ __forceinline__ LinkTile link_tile(const Geom& g, int linear, int ntiles, int split = 1) {
   const int tile = xcd_tile(linear, ntiles);
   LinkTile r;
   r.mu = tile & 3;
   r.p = (tile >> 2) & 1;
   int chunk = tile >> 3;
   if (g.tslab > 0) {
-    const int per = ntiles >> 6;  // chunks per XCD = tslab * cps
+    const int per = ntiles >> 6;  // chunks per XCD = tslab * cps * split
     const int xcd = chunk / per, j = chunk - xcd * per;
-    chunk = (xcd * g.tslab + j % g.tslab) * g.cps + j / g.tslab;
+    chunk = (xcd * g.tslab + j % g.tslab) * (g.cps * split) + j / g.tslab;
   }
   r.chunk = chunk;
   return r;
