@@ -412,7 +412,8 @@ def cpu_model():
 def cpu_baseline(U_np, L, u0, beta, one_thread_budget_s=8.0):
     """The FP64 oracle's force on every link of the workload with OpenMP on all host
     threads (the timed value; its forces and action are kept for the error report), and
-    on a random sample of links at one thread."""
+    on a random sample of links at one thread (the oracle's per-link gather, since the
+    whole-field scatter at one thread would take minutes)."""
     import numpy as np
 
     import oracle
@@ -445,9 +446,11 @@ def cpu_baseline(U_np, L, u0, beta, one_thread_budget_s=8.0):
         "unit": "link-forces/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"every link ({4 * V}) of the 32^3x64 workload, FP64, C oracle with OpenMP ({dt:.1f} s)",
+        "sample": f"every link ({4 * V}) of the 32^3x64 workload, FP64, C oracle with OpenMP: every loop "
+                  f"instance walked once, its staples scattered to its links ({dt:.1f} s)",
         "value_1_thread": n / dt1,
-        "sample_1_thread": f"{n} random links of the same workload, one thread ({dt1:.1f} s)",
+        "sample_1_thread": f"{n} random links of the same workload, one thread, each link's staples "
+                           f"gathered by the force algorithm's rotation rules ({dt1:.1f} s)",
         "host_threads": os.cpu_count(),
         "cpu_model": cpu_model(),
     }
@@ -545,6 +548,7 @@ def main():
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd timing")
     ap.add_argument("--only-f32", action="store_true", help="profiling runs: FP32 force only")
     ap.add_argument("--only-f64", action="store_true", help="profiling runs: FP64 force only")
+    ap.add_argument("--only-force", action="store_true", help="profiling runs: FP32 and FP64 force only")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the device peak measurements")
     args = ap.parse_args()
@@ -564,7 +568,7 @@ def main():
     import gaugegen
     import paper_1808_02281_amd as sym
 
-    if args.only_f32 or args.only_f64:
+    if args.only_f32 or args.only_f64 or args.only_force:
         args.no_cpu_baseline = args.no_md = args.no_batch = args.no_fat = True
         args.no_wilson = args.no_autograd = args.no_peaks = True
         args.no_fp64 = args.only_f32

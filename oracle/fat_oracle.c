@@ -15,10 +15,13 @@
  *   - the fat link V_{p,mu} = sum over the smearing paths P from p to p+mu of
  *     c_P times the product of links along P (eq. 18_6_6_7_2), and the Naik long link
  *     W_{p,mu} = c_N U_{p,mu} U_{p+mu,mu} U_{p+2mu,mu};
- *   - the derivative of a function of V through the smearing: F~ of eq. 18_7_24_7,
- *     computed by the enumerated algorithm after it (for every direction rho, every
- *     path, every link of the path along +-rho: A = product of the links before it,
- *     B = product of the links after it times F^T, accumulate).
+ *   - the derivative of a function of V through the smearing: F~ of eq. 18_7_24_7.
+ *     For the whole field every path instance is walked once and deposits, at each of
+ *     its links, the derivative of its trace with respect to that link (scatter);
+ *     single links are gathered by the enumerated algorithm after eq. 18_7_24_7 (for
+ *     every path link along +-rho: A = product of the links before it, B = product of
+ *     the links after it times F^T). The two formulations are checked against each
+ *     other.
  *
  * What is differentiated: the real scalar
  *     Phi(U) = Re sum_{p,mu} tr(GV_{p,mu}^dagger V_{p,mu}) + Re sum tr(GW^dagger W)
@@ -272,14 +275,97 @@ static mat3 grad_one(const lat *g, const double c[6], const cplx *U, const cplx 
     return acc;
 }
 
-/* grad_{k,rho} for every link (GW may be NULL: no Naik term). */
+/*
+ * Scatter form of the same gradient for the whole field, written from the definition
+ * of Phi: every path instance (base p, direction mu, path q) is walked once, links
+ * L_1 ... L_m, and for every position l
+ *     c_q tr(F^T L_1 ... L_m) = c_q tr(L_l R),  R = (L_{l+1} ... L_m) F^T (L_1 ... L_{l-1}),
+ * so dPhi = Re tr(grad^dagger dU) receives R^dagger at the link (n_l, rho) when
+ * d_l = +rho (L_l = U) and R at (n_l - rho, rho) when d_l = -rho (L_l = U^dagger).
+ */
+static void fat_deposit(const lat *g, const double c[6], const cplx *U, const cplx *G, int64_t p, int mu,
+                        const fpath *q, cplx *acc) {
+    mat3 Lk[FAT_MAXLEN];
+    int64_t recv[FAT_MAXLEN];
+    int64_t s = p;
+    for (int j = 0; j < q->len; ++j) {
+        Lk[j] = lnk(g, U, s, q->d[j]);
+        int64_t nx = hop(g, s, q->d[j]);
+        recv[j] = q->d[j] > 0 ? s * 4 + (q->d[j] - 1) : nx * 4 + (-q->d[j] - 1);
+        s = nx;
+    }
+    const mat3 Ft = dag3(ld3(G + (p * 4 + (mu - 1)) * 9));
+    for (int l = 0; l < q->len; ++l) {
+        mat3 R = one3();
+        for (int j = l + 1; j < q->len; ++j) R = mul3(R, Lk[j]);
+        R = mul3(R, Ft);
+        for (int j = 0; j < l; ++j) R = mul3(R, Lk[j]);
+        if (q->d[l] > 0) R = dag3(R);
+        st3(acc + recv[l] * 9, axpy3(ld3(acc + recv[l] * 9), c[q->cls], R));
+    }
+}
+
+/* Extent along t, relative to the base site, of the sites whose links the paths of
+ * every direction (the Naik path included) deposit to. */
+static void fat_t_extent(int *lo, int *hi) {
+    *lo = 0;
+    *hi = 0;
+    for (int mu = 1; mu <= 4; ++mu) {
+        fpath P[FAT_NPATH + 1];
+        int np = fat_paths(mu, P);
+        fpath naik = {3, FAT_NAIK, {mu, mu, mu}};
+        P[np++] = naik;
+        for (int i = 0; i < np; ++i) {
+            int t = 0;
+            for (int j = 0; j < P[i].len; ++j) {
+                int d = P[i].d[j];
+                int nt = t + (d == 4 ? 1 : d == -4 ? -1 : 0);
+                int r = d > 0 ? t : nt;
+                if (r < *lo) *lo = r;
+                if (r > *hi) *hi = r;
+                t = nt;
+            }
+        }
+    }
+}
+
+static void fat_deposit_site(const lat *g, const double c[6], const cplx *U, const cplx *GV, const cplx *GW,
+                             int64_t p, cplx *acc) {
+    for (int mu = 1; mu <= 4; ++mu) {
+        fpath P[FAT_NPATH];
+        int np = fat_paths(mu, P);
+        for (int i = 0; i < np; ++i) fat_deposit(g, c, U, GV, p, mu, &P[i], acc);
+        if (GW != NULL) {
+            fpath naik = {3, FAT_NAIK, {mu, mu, mu}};
+            fat_deposit(g, c, U, GW, p, mu, &naik, acc);
+        }
+    }
+}
+
+/* grad_{k,rho} for every link (GW may be NULL: no Naik term), by the scatter above.
+ * Base sites go t-slice by t-slice in phases whose slices are far enough apart to
+ * deposit to disjoint slices (parallel inside a phase, the same order of deposits at
+ * every link whatever the thread count); lattices short in t run serially. */
 void orc_fat_grad(const int32_t L[4], const double c[6], const cplx *U, const cplx *GV, const cplx *GW,
                   cplx *grad) {
     lat g = mklat(L);
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t k = 0; k < g.V * 4; ++k) {
-        mat3 r = grad_one(&g, c, U, GV, GW, k / 4, (int)(k % 4) + 1);
-        st3(grad + k * 9, r);
+    memset(grad, 0, sizeof(cplx) * 9 * 4 * (size_t)g.V);
+    int lo, hi;
+    fat_t_extent(&lo, &hi);
+    const int Lt = g.L[3];
+    int nph = hi - lo + 1;
+    while (nph < Lt && Lt % nph != 0) ++nph;
+    const int64_t per = g.V / Lt;
+    if (Lt < 2 * nph) {
+        for (int64_t p = 0; p < g.V; ++p) fat_deposit_site(&g, c, U, GV, GW, p, grad);
+        return;
+    }
+    for (int phase = 0; phase < nph; ++phase) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int q = 0; q < Lt / nph; ++q) {
+            const int64_t t = (int64_t)q * nph + phase;
+            for (int64_t p = t * per; p < (t + 1) * per; ++p) fat_deposit_site(&g, c, U, GV, GW, p, grad);
+        }
     }
 }
 

@@ -18,11 +18,15 @@
  *   - loop products P_n = U_{n1,d1}...U_{nL,dL}: eq. (18_6_6_3_0), with
  *     U_{n,-mu} = U^dagger_{n-mu,mu};
  *   - action S_G = beta/3 sum_n sum_P c_P [3 - Re tr P_n]: eq. (18_6_4_1);
- *   - force: the enumerated gauge-force algorithm after eq. (18_6_6_13): for each
- *     link (k,rho), t = sum over loops and over positions l with d_l = +rho or -rho
- *     of c_P times the staple; the force is (beta/6) i (U_{k,rho} t)_TA with the TA
- *     projection of eq. (18_6_6_11). This file returns G = (beta/6)(U t)_TA, the
- *     antihermitian matrix; the paper's Hermitian force is iG.
+ *   - force: (beta/6) i (U_{k,rho} t_{k,rho})_TA with the TA projection of
+ *     eq. (18_6_6_11), where t_{k,rho} collects, with weight c_P, the derivative of
+ *     Re tr P_n with respect to U_{k,rho} for every loop instance through the link
+ *     (eq. 18_7_25_2). The whole field is built by scattering: each loop instance is
+ *     walked once and deposits its staple into every link it contains. Single links
+ *     are gathered by the rotation rules of the force algorithm after eq. (18_6_6_13)
+ *     (staple from k+rho, reversed and daggered for d_l = -rho); the two formulations
+ *     share only the loop walk and are checked against each other. This file returns
+ *     G = (beta/6)(U t)_TA, the antihermitian matrix; the paper's Hermitian force is iG.
  *
  * Parity-relevant readings of the paper (listed with the rest in the design notes):
  *   - U_{n,mu} lives on the link (n, n+mu) (the paper's text has a typo there);
@@ -296,7 +300,9 @@ static mat3 staple(const lattice *g, const cplx *U, int64_t k, int rho, const lo
     return r;
 }
 
-/* t_{k,rho} split by loop class (unweighted); the force uses sum_cls c[cls] t[cls]. */
+/* t_{k,rho} split by loop class (unweighted), gathered link by link: every (loop,
+ * position) pair whose link runs along +-rho names one staple of (k,rho). Used for
+ * the force on a list of links; the whole field is built by the scatter below. */
 static void staple_sums(const lattice *g, const cplx *U, const loop_t *lp, int np, int64_t k,
                         int rho, mat3 t[3]) {
     for (int c = 0; c < 3; ++c) t[c] = m_zero();
@@ -316,18 +322,101 @@ static mat3 force_one(const lattice *g, const cplx *U, const loop_t *lp, int np,
     return m_scale(m_ta(m_mul(u, tw)), beta / 6.0);
 }
 
-/* G_{k,rho} = (beta/6)(U_{k,rho} t_{k,rho})_TA for every link. */
+/*
+ * Scatter form of the staple sums, written from the action itself (eq. 18_6_4_1) and
+ * the derivative of eq. (18_7_25_2): every loop instance P_n = L_1 ... L_m is walked
+ * once from its base site n, and for every position j the derivative of Re tr P_n
+ * with respect to the link that L_j stands for is deposited into that link's t:
+ *   tr P_n = tr(L_j A_j),  A_j = L_{j+1} ... L_m L_1 ... L_{j-1}  (cyclic order);
+ *   d_j = +mu: L_j = U_{n_j,mu},            Re tr P_n = Re tr(U A_j),   deposit A_j   at (n_j, mu);
+ *   d_j = -mu: L_j = U^dag_{n_j - mu, mu},  Re tr P_n = Re tr(U A_j^dag), deposit A_j^dag at (n_j - mu, mu).
+ * acc holds ncls matrices per link, acc[((site*4 + mu)*ncls + slot)*9], where slot is
+ * the loop's class (ncls = 3, weight 1) or 0 (ncls = 1, weight w[class]).
+ */
+static void deposit_loop(const lattice *g, const cplx *U, int64_t n, const loop_t *p, int ncls,
+                         const double w[3], cplx *acc) {
+    mat3 Lk[6];
+    int64_t recv[6];
+    int64_t s = n;
+    for (int j = 0; j < p->len; ++j) {
+        Lk[j] = link(g, U, s, p->d[j]);
+        int64_t nx = step(g, s, p->d[j]);
+        recv[j] = p->d[j] > 0 ? s * 4 + (p->d[j] - 1) : nx * 4 + (-p->d[j] - 1);
+        s = nx;
+    }
+    const int slot = ncls == 1 ? 0 : p->cls;
+    const double wt = ncls == 1 ? w[p->cls] : 1.0;
+    for (int j = 0; j < p->len; ++j) {
+        mat3 a = m_unit();
+        for (int i = 1; i < p->len; ++i) a = m_mul(a, Lk[(j + i) % p->len]);
+        if (p->d[j] < 0) a = m_dag(a);
+        cplx *dst = acc + (recv[j] * ncls + slot) * 9;
+        m_store(dst, m_add_scaled(m_load(dst), wt, a));
+    }
+}
+
+/* Extent along t, relative to the base site, of the sites whose links a loop deposits to. */
+static void deposit_t_extent(const loop_t *lp, int np, int *lo, int *hi) {
+    *lo = 0;
+    *hi = 0;
+    for (int p = 0; p < np; ++p) {
+        int t = 0;
+        for (int j = 0; j < lp[p].len; ++j) {
+            int d = lp[p].d[j];
+            int nt = t + (d == 4 ? 1 : d == -4 ? -1 : 0);
+            int r = d > 0 ? t : nt; /* receiving site of position j */
+            if (r < *lo) *lo = r;
+            if (r > *hi) *hi = r;
+            t = nt;
+        }
+    }
+}
+
+/*
+ * acc (zeroed by the caller) += the deposits of every loop instance. Base sites are
+ * taken t-slice by t-slice in `nph` phases, nph the smallest divisor of Lt not below
+ * the deposit extent: the slices of one phase are nph apart, deposit to disjoint
+ * slices and run in parallel, and every link receives its deposits in the same order
+ * whatever the thread count. Lattices too short in t for two slices per phase run
+ * serially.
+ */
+static void scatter_staples(const lattice *g, const cplx *U, const loop_t *lp, int np, int ncls,
+                            const double w[3], cplx *acc) {
+    int lo, hi;
+    deposit_t_extent(lp, np, &lo, &hi);
+    const int Lt = g->L[3];
+    int nph = hi - lo + 1;
+    while (nph < Lt && Lt % nph != 0) ++nph;
+    const int64_t per = g->V / Lt; /* sites per t-slice */
+    if (Lt < 2 * nph) {
+        for (int64_t n = 0; n < g->V; ++n)
+            for (int p = 0; p < np; ++p) deposit_loop(g, U, n, &lp[p], ncls, w, acc);
+        return;
+    }
+    for (int phase = 0; phase < nph; ++phase) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int q = 0; q < Lt / nph; ++q) {
+            const int64_t t = (int64_t)q * nph + phase;
+            for (int64_t n = t * per; n < (t + 1) * per; ++n)
+                for (int p = 0; p < np; ++p) deposit_loop(g, U, n, &lp[p], ncls, w, acc);
+        }
+    }
+}
+
+/* G_{k,rho} = (beta/6)(U_{k,rho} t_{k,rho})_TA for every link, t from the scatter. */
 void orc_force(const int32_t L[4], const double c[3], double beta, const cplx *U, cplx *G) {
     lattice g = make_lattice(L);
     loop_t lp[34];
     int np = build_loops(lp);
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t k = 0; k < g.V; ++k)
-        for (int rho = 0; rho < 4; ++rho)
-            m_store(G + (k * 4 + rho) * 9, force_one(&g, U, lp, np, c, beta, k, rho));
+    memset(G, 0, sizeof(cplx) * 9 * 4 * (size_t)g.V);
+    scatter_staples(&g, U, lp, np, 1, c, G);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < 4 * g.V; ++i)
+        m_store(G + i * 9, m_scale(m_ta(m_mul(m_load(U + i * 9), m_load(G + i * 9))), beta / 6.0));
 }
 
-/* The same force for a list of links only (sampled checks on large lattices). */
+/* The same force for a list of links only, gathered link by link (sampled checks on
+ * large lattices; a second formulation of the staple sums beside the scatter). */
 void orc_force_links(const int32_t L[4], const double c[3], double beta, const cplx *U,
                      int64_t nlinks, const int64_t *site, const int32_t *mu, cplx *G) {
     lattice g = make_lattice(L);
@@ -343,13 +432,9 @@ void orc_staple_sums(const int32_t L[4], const cplx *U, cplx *out) {
     lattice g = make_lattice(L);
     loop_t lp[34];
     int np = build_loops(lp);
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t k = 0; k < g.V; ++k)
-        for (int rho = 0; rho < 4; ++rho) {
-            mat3 t[3];
-            staple_sums(&g, U, lp, np, k, rho, t);
-            for (int cl = 0; cl < 3; ++cl) m_store(out + ((k * 4 + rho) * 3 + cl) * 9, t[cl]);
-        }
+    const double one[3] = {1.0, 1.0, 1.0};
+    memset(out, 0, sizeof(cplx) * 9 * 3 * 4 * (size_t)g.V);
+    scatter_staples(&g, U, lp, np, 3, one, out);
 }
 
 /*

@@ -271,15 +271,22 @@ def test_local_action_carries_the_link_dependence(coeffs):
     assert abs(dS - dl) < 1e-10
 
 
-def test_force_links_equals_full_force(coeffs):
-    L = (4, 4, 4, 4)
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (4, 6, 4, 6), (4, 4, 6, 8)])
+def test_force_links_equals_full_force(coeffs, L):
+    """The whole field comes from the loop scatter (each loop instance deposits its
+    staple into every link it contains), single links from the gather by the rotation
+    rules of the force algorithm: the two formulations agree on every link, to
+    rounding. (4,4,6,8) takes the scatter's parallel t-slice phases, the other two its
+    serial order."""
     U = gaugegen.haar_links(L, 0)
-    G = oracle.force(U, L, coeffs, BETA)
-    sites = np.array([0, 17, 255, 128])
-    mus = np.array([0, 3, 1, 2])
+    V = int(np.prod(L))
+    G = oracle.force(U, L, coeffs, BETA).reshape(V, 4, 3, 3)
+    sites = np.repeat(np.arange(V), 4)
+    mus = np.tile(np.arange(4), V)
     Gs = oracle.force_links(U, L, coeffs, BETA, sites, mus)
-    flat = G.reshape(256, 4, 3, 3)
-    np.testing.assert_array_equal(Gs, flat[sites, mus])
+    err = np.abs(Gs - G[sites, mus]).max() / np.abs(G).max()
+    assert err < 1e-13
+    assert np.abs(G).max() > 0.1
 
 
 # ---------------------------------------------------------------- exponential map
