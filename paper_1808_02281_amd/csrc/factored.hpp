@@ -315,18 +315,23 @@ struct StapleStep {
 };
 constexpr int kStapleSteps = 18;
 
+// What one step loads: the two links besides the site's own, and, with the first step
+// of a backward group (J = 0), w_A = U_{x-A,A}. The site's own u_a stay in registers
+// through the forward steps only, and one w_A at a time through its group (FP64, one
+// step ahead: 269 registers instead of 380), which leaves room to run the loads three
+// steps ahead at one wave per SIMD (424 registers; FP32 192, two waves).
 template <typename T>
-struct LinkPair {
-  Rows2<T> a, b;
+struct StepData {
+  Rows2<T> a, b, w;
 };
 
 template <int K, typename T>
-__device__ __forceinline__ LinkPair<T> load_step(const SCtx<T>& c0) {
+__device__ __forceinline__ StepData<T> load_step(const SCtx<T>& c0) {
   SCtx<T> c = c0;
   launder(c);
   using St = StapleStep<K>;
   constexpr int MU = St::MU, A = St::A;
-  LinkPair<T> d;
+  StepData<T> d;
   if constexpr (St::fwd) {
     d.a = c.template link<A, unit(0, MU), unit(1, MU), unit(2, MU), unit(3, MU)>();  // U_{x+MU,A}
     d.b = c.template link<MU, unit(0, A), unit(1, A), unit(2, A), unit(3, A)>();     // U_{x+A,MU}
@@ -334,13 +339,15 @@ __device__ __forceinline__ LinkPair<T> load_step(const SCtx<T>& c0) {
     d.a = c.template link<A, unit(0, MU) - unit(0, A), unit(1, MU) - unit(1, A), unit(2, MU) - unit(2, A),
                           unit(3, MU) - unit(3, A)>();                               // U_{x+MU-A,A}
     d.b = c.template link<MU, -unit(0, A), -unit(1, A), -unit(2, A), -unit(3, A)>();  // U_{x-A,MU}
+    if constexpr (St::J == 0)
+      d.w = c.template link<A, -unit(0, A), -unit(1, A), -unit(2, A), -unit(3, A)>();  // U_{x-A,A}
   }
   return d;
 }
 
 template <int K, int POL, typename T>
-__device__ __forceinline__ void use_step(const SCtx<T>& c, const Rows2<T> (&u)[4], const Rows2<T> (&w)[4],
-                                         const LinkPair<T>& d) {
+__device__ __forceinline__ void use_step(const SCtx<T>& c, const Rows2<T> (&u)[4], const Rows2<T>& wA,
+                                         const StepData<T>& d) {
   using St = StapleStep<K>;
   constexpr int MU = St::MU, A = St::A;
   if constexpr (St::fwd) {
@@ -352,25 +359,32 @@ __device__ __forceinline__ void use_step(const SCtx<T>& c, const Rows2<T> (&u)[4
     Rows2<T> nr;
 #pragma unroll
     for (int i = 0; i < 6; ++i) nr.e[i] = n.e[i];
-    store_staple<T, POL>(c.S8, c.Ss, MU, c.p, 2 * A + 1, c.cb, rows_mul<false>(nr, full(w[A])));
+    store_staple<T, POL>(c.S8, c.Ss, MU, c.p, 2 * A + 1, c.cb, rows_mul<false>(nr, full(wA)));
   }
 }
 
-// Software-pipelined: the links of step K+1 are requested before the staples of step K
-// are formed and stored. Vector memory operations complete in issue order, so a load
-// issued after a store would wait for it (0.82 -> 0.79 ms FP32, 1.46 -> 1.42 ms FP64 on
-// the 32^3 x 64 workload).
+// Software-pipelined: the links of step K+3 are requested before the staples of step K
+// are formed and stored (vector memory operations complete in issue order, so a load
+// issued after a store would wait for it). On the 32^3 x 64 workload: one step ahead
+// 0.82 -> 0.79 ms FP32, 1.46 -> 1.42 ms FP64; three steps ahead with the lean register
+// set 1.44 -> 1.41 ms FP64 (FP32 unchanged). n1, n2 hold the two steps already loaded.
+constexpr int kStapleAhead = 3;
+
 template <int K, int POL, typename T>
-__device__ __forceinline__ void staple_pipe(const SCtx<T>& c, const Rows2<T> (&u)[4], const Rows2<T> (&w)[4],
-                                            const LinkPair<T>& cur) {
-  if constexpr (K + 1 < kStapleSteps) {
-    const LinkPair<T> nxt = load_step<K + 1>(c);
+__device__ __forceinline__ void staple_pipe(const SCtx<T>& c, const Rows2<T> (&u)[4], const Rows2<T>& wprev,
+                                            const StepData<T>& cur, const StepData<T>& n1, const StepData<T>& n2) {
+  using St = StapleStep<K>;
+  const Rows2<T>& wA = (!St::fwd && St::J == 0) ? cur.w : wprev;
+  if constexpr (K + kStapleAhead < kStapleSteps) {
+    const StepData<T> n3 = load_step<K + kStapleAhead>(c);
     SYM_FENCE();
-    use_step<K, POL>(c, u, w, cur);
+    use_step<K, POL>(c, u, wA, cur);
     SYM_FENCE();
-    staple_pipe<K + 1, POL>(c, u, w, nxt);
+    staple_pipe<K + 1, POL>(c, u, wA, n1, n2, n3);
   } else {
-    use_step<K, POL>(c, u, w, cur);
+    use_step<K, POL>(c, u, wA, cur);
+    SYM_FENCE();
+    if constexpr (K + 1 < kStapleSteps) staple_pipe<K + 1, POL>(c, u, wA, n1, n2, n2);  // last argument unused
   }
 }
 
@@ -388,18 +402,16 @@ __device__ __forceinline__ void staples_site(const Geom& g, const T* U, T* S8, i
   c.p = p;
   c.cb = cb;
   make_nbr(g, x, c.nb);
-  Rows2<T> u[4], w[4];
+  Rows2<T> u[4];
   u[0] = c.template link<0, 0, 0, 0, 0>();
   u[1] = c.template link<1, 0, 0, 0, 0>();
   u[2] = c.template link<2, 0, 0, 0, 0>();
   u[3] = c.template link<3, 0, 0, 0, 0>();
-  w[0] = c.template link<0, -1, 0, 0, 0>();
-  w[1] = c.template link<1, 0, -1, 0, 0>();
-  w[2] = c.template link<2, 0, 0, -1, 0>();
-  w[3] = c.template link<3, 0, 0, 0, -1>();
-  const LinkPair<T> d0 = load_step<0>(c);
+  const StepData<T> d0 = load_step<0>(c);
+  const StepData<T> d1 = load_step<1>(c);
+  const StepData<T> d2 = load_step<2>(c);
   SYM_FENCE();
-  staple_pipe<0, POL>(c, u, w, d0);
+  staple_pipe<0, POL>(c, u, d0.w, d0, d1, d2);  // d0.w unused: step 0 is a forward step
 }
 
 
