@@ -137,6 +137,28 @@ struct FCtx {
     return load_su3_rows(block_ptr(U, axis[AX], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
   }
 
+  // the first two rows of U_{x+d, axis[AX]}, loaded only (rebuilt where used, so that
+  // the loads can be issued ahead of their use like the staples')
+  template <int D0, int D1, int D2, int D3, int AX>
+  __device__ __forceinline__ Rows2<T> link_rows2() const {
+    constexpr int dp = offset_parity<D0, D1, D2, D3>();
+    const cx<T>* blk = block_ptr(U, axis[AX], p ^ dp, Vh);
+    const unsigned bytes = 6u * (unsigned)Vh * (unsigned)sizeof(cx<T>);
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(blk), (short)0, (int)bytes, kBufferWord3);
+    const int voff = nbr_cb<D0, D1, D2, D3>(nb) * (int)sizeof(cx<T>);
+    Rows2<T> u;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int soff = (int)((unsigned)e * (unsigned)Vh * (unsigned)sizeof(cx<T>));
+      if constexpr (sizeof(T) == 4)
+        u.e[e] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+      else
+        u.e[e] = __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+    return u;
+  }
+
   // the first two rows of S(x+d, axis[AX], e), e = sign ES along frame axis EAX, loaded
   // only (the third row is rebuilt where the matrix is used, so that the loads can be
   // issued well ahead of their use)
@@ -417,140 +439,201 @@ __device__ __forceinline__ void staples_site(const Geom& g, const T* U, T* S8, i
 
 // ---------------------------------------------------------------- pass 2
 
-// Short-side rectangles and cube loops (mixed factorisation, see the top of the file),
-// software-pipelined item by item: the loads of item K+1 are issued before item K is
-// multiplied out. Items K = 3F + k for F = 0..5 (f = e_F): k = 0, 1 the triple
-// (S(x+f,mu,e), S(x,f,e), S(x+mu,f,e)) for e = +-(next frame axis); k = 2 the short
-// side (S(x+f,mu,f), U_{x+f,-f}, U_{x+mu,f}) and the outer products of f.
+// Pass 2 runs as one software pipeline of kSteps steps; the loads of step S+1 are
+// issued before step S is multiplied out (vector memory operations complete in issue
+// order, so the loads of the next step never wait for the stores or products of this
+// one). Every matrix is loaded as its first two rows and rebuilt where it is used.
+//   S = 0..5   long side, e = e_S: tP += S(x,mu,e), RA += S(x+mu,mu,e) S(x,mu,e),
+//              RB += S(x,mu,e) S(x-mu,mu,e);
+//   S = 6      U_{x,mu}, U_{x+-mu,mu}: plaquette and long-side rectangle parts of t and
+//              their deficit partials;
+//   S = 7..24  items K = S - 7 = 3F + k, f = e_F: k = 0, 1 the triple (S(x+f,mu,e),
+//              S(x,f,e), S(x+mu,f,e)) for e = +-(next frame axis) into QA_f, QB_f;
+//              k = 2 the short side (S(x+f,mu,f), U_{x+f,-f}, U_{x+mu,f}) and the outer
+//              products of f (mixed factorisation, see the top of the file);
+//   S = 25     U_{x,mu} again: B = U t, the force epilogue and the last partial.
+// One pipeline across the phases, with the short-side links rebuilt at use rather than
+// on load, took the pass from 2.43 to 2.38 ms (FP32) and 5.27 to 5.12 ms (FP64) on the
+// 32^3 x 64 workload; loading two or three steps ahead was not faster.
 constexpr int next_axis(int a) { return a == 3 ? 1 : a + 1; }
-constexpr int kItems = 18;
+constexpr int kSteps = 26;
 
+template <typename T>
+struct LongSide {
+  Rows2<T> sx, sp, sm;  // S(x,mu,e), S(x+mu,mu,e), S(x-mu,mu,e)
+};
+template <typename T>
+struct Middle {
+  Rows2<T> u, up, um;   // U_{x,mu}, U_{x+mu,mu}, U_{x-mu,mu}
+};
 template <typename T>
 struct Triple {
   Rows2<T> m, a, b;  // S(x+f,mu,e); S(x,f,e) (or its dagger's storage); S(x+mu,f,e) (likewise)
 };
 template <typename T>
 struct Short {
-  Rows2<T> see;      // S(x+f,mu,f)
-  su3<T> lnk, uxm;   // U_{x,a} or U_{x-a,a}; U_{x+mu,a} or U_{x+mu-a,a}  (f = +-a)
+  Rows2<T> see;       // S(x+f,mu,f)
+  Rows2<T> lnk, uxm;  // U_{x,a} or U_{x-a,a}; U_{x+mu,a} or U_{x+mu-a,a}  (f = +-a)
+};
+template <typename T>
+struct Last {
+  Rows2<T> u;  // U_{x,mu}
 };
 
-template <int K, typename T>
-__device__ __forceinline__ auto load_item(const FCtx<T>& c0) {
+// Per-link state of the pipeline.
+template <typename T>
+struct FState {
+  su3<T> tP, RA, RB, t, QA, QB;
+  double part;  // Re tr(U t) before the short-side rectangles and cubes are added
+  double a[3];
+  T cP, cR, cC;
+  double beta, kick;
+  T* out;
+  int Vh, mu, p, cb;
+};
+
+template <int S, typename T>
+__device__ __forceinline__ auto load_fstep(const FCtx<T>& c0) {
   FCtx<T> c = c0;
   launder(c);
-  constexpr int F = K / 3, k = K % 3;
-  constexpr int fa = e_axis(F), fs = e_sign(F);
-  constexpr int f1 = fs * comp(1, fa), f2 = fs * comp(2, fa), f3 = fs * comp(3, fa);
-  if constexpr (k < 2) {
-    constexpr int ea = next_axis(fa), es = k == 0 ? 1 : -1;
-    Triple<T> d;
-    d.m = c.template stap_rows<0, f1, f2, f3, 0, ea, es>();  // S(x+f, mu, e)
-    // S(x, f, e) and S(x+mu, f, e): for f = -a stored as S(x-a, a, e)^dagger and
-    // S(x+mu-a, a, e)^dagger
-    d.a = c.template stap_rows<0, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
-    d.b = c.template stap_rows<1, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
+  if constexpr (S < 6) {
+    constexpr int a = e_axis(S), s = e_sign(S);
+    LongSide<T> d;
+    d.sx = c.template stap_rows<0, 0, 0, 0, 0, a, s>();
+    d.sp = c.template stap_rows<1, 0, 0, 0, 0, a, s>();
+    d.sm = c.template stap_rows<-1, 0, 0, 0, 0, a, s>();
     return d;
-  } else {
-    Short<T> d;
-    d.see = c.template stap_rows<0, f1, f2, f3, 0, fa, fs>();
-    if constexpr (fs > 0) {
-      d.lnk = c.template link_rows<0, 0, 0, 0, fa>();
-      d.uxm = c.template link_rows<1, 0, 0, 0, fa>();
+  } else if constexpr (S == 6) {
+    Middle<T> d;
+    d.u = c.template link_rows2<0, 0, 0, 0, 0>();
+    d.up = c.template link_rows2<1, 0, 0, 0, 0>();
+    d.um = c.template link_rows2<-1, 0, 0, 0, 0>();
+    return d;
+  } else if constexpr (S < kSteps - 1) {
+    constexpr int K = S - 7, F = K / 3, k = K % 3;
+    constexpr int fa = e_axis(F), fs = e_sign(F);
+    constexpr int f1 = fs * comp(1, fa), f2 = fs * comp(2, fa), f3 = fs * comp(3, fa);
+    if constexpr (k < 2) {
+      constexpr int ea = next_axis(fa), es = k == 0 ? 1 : -1;
+      Triple<T> d;
+      d.m = c.template stap_rows<0, f1, f2, f3, 0, ea, es>();  // S(x+f, mu, e)
+      // S(x, f, e) and S(x+mu, f, e): for f = -a stored as S(x-a, a, e)^dagger and
+      // S(x+mu-a, a, e)^dagger
+      d.a = c.template stap_rows<0, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
+      d.b = c.template stap_rows<1, (fs < 0 ? f1 : 0), (fs < 0 ? f2 : 0), (fs < 0 ? f3 : 0), fa, ea, es>();
+      return d;
     } else {
-      d.lnk = c.template link_rows<0, f1, f2, f3, fa>();
-      d.uxm = c.template link_rows<1, f1, f2, f3, fa>();
+      Short<T> d;
+      d.see = c.template stap_rows<0, f1, f2, f3, 0, fa, fs>();
+      if constexpr (fs > 0) {
+        d.lnk = c.template link_rows2<0, 0, 0, 0, fa>();
+        d.uxm = c.template link_rows2<1, 0, 0, 0, fa>();
+      } else {
+        d.lnk = c.template link_rows2<0, f1, f2, f3, fa>();
+        d.uxm = c.template link_rows2<1, f1, f2, f3, fa>();
+      }
+      return d;
     }
+  } else {
+    Last<T> d;
+    d.u = c.template link_rows2<0, 0, 0, 0, 0>();
     return d;
   }
 }
 
-template <int K, typename T, typename It>
-__device__ __forceinline__ void use_item(su3<T>& t, su3<T>& QA, su3<T>& QB, const It& d, T cR, T cC) {
-  constexpr int F = K / 3, k = K % 3;
-  constexpr int fs = e_sign(F);
-  if constexpr (k < 2) {
-    if constexpr (k == 0) {
-      set_zero(QA);
-      set_zero(QB);
-    }
-    // every factor is special unitary, so is every product: two rows are multiplied
-    // out and the third rebuilt
-    const su3<T> m = full(d.m);
-    if constexpr (fs > 0) {
-      add(QA, full(rows_mul<false>(d.m, full(d.a))));   // S(x+f,mu,e) S(x,a,e)
-      add(QB, full(rows_mul2<true, false>(full(d.b), m)));  // S(x+mu,a,e)^dagger S(x+f,mu,e)
-    } else {
-      add(QA, full(rows_mul<true>(d.m, full(d.a))));    // S(x+f,mu,e) S(x-a,a,e)^dagger
-      add(QB, full(rows_mul<false>(d.b, m)));           // S(x+mu-a,a,e) S(x+f,mu,e)
-    }
-  } else {
-    su3<T> R = full(rows_mul<(fs > 0)>(d.see, d.lnk));  // S(x+f,mu,f) U_{x+f,-f}
+template <int S, ForceOut MODE, typename T, typename D>
+__device__ __forceinline__ void use_fstep(FState<T>& st, const D& d) {
+  if constexpr (S < 6) {
+    const su3<T> sx = full(d.sx);
+    add(st.tP, sx);
+    add(st.RA, full(rows_mul<false>(d.sp, sx)));
+    mac<false, false>(st.RB, sx, full(d.sm));
+  } else if constexpr (S == 6) {
+    const su3<T> u = full(d.u);
+    su3<T> WR = mul<false, false>(full(d.up), st.RA);  // U_{x+mu,mu} RA
+    mac<false, false>(WR, st.RB, full(d.um));          // + RB U_{x-mu,mu}
+    st.a[0] = 18.0 - re_tr_mul(u, st.tP);
+    st.a[1] = 36.0 - re_tr_mul(u, WR);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      R.e[i].re = fma(cC, QA.e[i].re, cR * R.e[i].re);
-      R.e[i].im = fma(cC, QA.e[i].im, cR * R.e[i].im);
-      QB.e[i].re *= cC;
-      QB.e[i].im *= cC;
+      st.t.e[i].re = fma(st.cP, st.tP.e[i].re, st.cR * WR.e[i].re);
+      st.t.e[i].im = fma(st.cP, st.tP.e[i].im, st.cR * WR.e[i].im);
     }
-    if constexpr (fs > 0) {
-      mac<false, false>(t, d.uxm, R);
-      mac<false, true>(t, QB, d.lnk);
+    st.part = double(st.cP) * (18.0 - st.a[0]) + double(st.cR) * (36.0 - st.a[1]);
+  } else if constexpr (S < kSteps - 1) {
+    constexpr int K = S - 7, F = K / 3, k = K % 3;
+    constexpr int fs = e_sign(F);
+    if constexpr (k < 2) {
+      if constexpr (k == 0) {
+        set_zero(st.QA);
+        set_zero(st.QB);
+      }
+      // every factor is special unitary, so is every product: two rows are multiplied
+      // out and the third rebuilt
+      const su3<T> m = full(d.m);
+      if constexpr (fs > 0) {
+        add(st.QA, full(rows_mul<false>(d.m, full(d.a))));      // S(x+f,mu,e) S(x,a,e)
+        add(st.QB, full(rows_mul2<true, false>(full(d.b), m)));  // S(x+mu,a,e)^dagger S(x+f,mu,e)
+      } else {
+        add(st.QA, full(rows_mul<true>(d.m, full(d.a))));  // S(x+f,mu,e) S(x-a,a,e)^dagger
+        add(st.QB, full(rows_mul<false>(d.b, m)));         // S(x+mu-a,a,e) S(x+f,mu,e)
+      }
     } else {
-      mac<true, false>(t, d.uxm, R);
-      mac<false, false>(t, QB, d.lnk);
+      const su3<T> lnk = full(d.lnk), uxm = full(d.uxm);
+      su3<T> R = full(rows_mul<(fs > 0)>(d.see, lnk));  // S(x+f,mu,f) U_{x+f,-f}
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        R.e[i].re = fma(st.cC, st.QA.e[i].re, st.cR * R.e[i].re);
+        R.e[i].im = fma(st.cC, st.QA.e[i].im, st.cR * R.e[i].im);
+        st.QB.e[i].re *= st.cC;
+        st.QB.e[i].im *= st.cC;
+      }
+      if constexpr (fs > 0) {
+        mac<false, false>(st.t, uxm, R);
+        mac<false, true>(st.t, st.QB, lnk);
+      } else {
+        mac<true, false>(st.t, uxm, R);
+        mac<false, false>(st.t, st.QB, lnk);
+      }
+    }
+  } else {
+    const su3<T> u = full(d.u);
+    const su3<T> B = mul<false, false>(u, st.t);
+    st.a[2] = 18.0 * double(st.cR) + 72.0 * double(st.cC) - (re_tr(B) - st.part);
+    const su3<T> G = ta_scaled(B, T(st.beta / 6.0));
+    cx<T>* dst = block_ptr(st.out, st.mu, st.p, st.Vh);
+    if constexpr (MODE == ForceOut::Store) {
+      store_link(dst, st.Vh, st.cb, G);
+    } else if constexpr (MODE == ForceOut::Grad) {
+      su3<T> gr = mul<false, false>(G, u);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        gr.e[e].re *= T(2);
+        gr.e[e].im *= T(2);
+      }
+      store_link(dst, st.Vh, st.cb, gr);
+    } else {
+      su3<T> q = load_link(static_cast<const cx<T>*>(dst), st.Vh, st.cb);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        q.e[e].re = T(double(q.e[e].re) - st.kick * double(G.e[e].re));
+        q.e[e].im = T(double(q.e[e].im) - st.kick * double(G.e[e].im));
+      }
+      store_link(dst, st.Vh, st.cb, q);
     }
   }
 }
 
-template <int K, typename T, typename It>
-__device__ __forceinline__ void items_pipe(const FCtx<T>& c, su3<T>& t, su3<T>& QA, su3<T>& QB, const It& cur, T cR,
-                                           T cC) {
-  if constexpr (K + 1 < kItems) {
-    const auto nxt = load_item<K + 1>(c);
+template <int S, ForceOut MODE, typename T, typename D>
+__device__ __forceinline__ void force_pipe(const FCtx<T>& c, FState<T>& st, const D& cur) {
+  if constexpr (S + 1 < kSteps) {
+    const auto nxt = load_fstep<S + 1>(c);
     SYM_FENCE();
-    use_item<K>(t, QA, QB, cur, cR, cC);
+    use_fstep<S, MODE>(st, cur);
     SYM_FENCE();
-    items_pipe<K + 1>(c, t, QA, QB, nxt, cR, cC);
+    force_pipe<S + 1, MODE>(c, st, nxt);
   } else {
-    use_item<K>(t, QA, QB, cur, cR, cC);
-  }
-}
-
-// Long-side rectangles, RA += S(x+mu,mu,e) S(x,mu,e), RB += S(x,mu,e) S(x-mu,mu,e),
-// tP += S(x,mu,e), software-pipelined: the three staples of e_{J+1} are requested
-// before those of e_J are multiplied out.
-template <typename T>
-struct LongSide {
-  Rows2<T> sx, sp, sm;  // S(x,mu,e), S(x+mu,mu,e), S(x-mu,mu,e)
-};
-template <int J, typename T>
-__device__ __forceinline__ LongSide<T> load_long(const FCtx<T>& c0) {
-  FCtx<T> c = c0;
-  launder(c);
-  constexpr int a = e_axis(J), s = e_sign(J);
-  LongSide<T> d;
-  d.sx = c.template stap_rows<0, 0, 0, 0, 0, a, s>();
-  d.sp = c.template stap_rows<1, 0, 0, 0, 0, a, s>();
-  d.sm = c.template stap_rows<-1, 0, 0, 0, 0, a, s>();
-  return d;
-}
-template <int J, typename T>
-__device__ __forceinline__ void long_pipe(const FCtx<T>& c, su3<T>& tP, su3<T>& RA, su3<T>& RB, const LongSide<T>& d) {
-  if constexpr (J < 5) {
-    const LongSide<T> dn = load_long<J + 1>(c);
-    SYM_FENCE();
-    const su3<T> sx = full(d.sx);
-    add(tP, sx);
-    add(RA, full(rows_mul<false>(d.sp, sx)));
-    mac<false, false>(RB, sx, full(d.sm));
-    SYM_FENCE();
-    long_pipe<J + 1>(c, tP, RA, RB, dn);
-  } else {
-    const su3<T> sx = full(d.sx);
-    add(tP, sx);
-    add(RA, full(rows_mul<false>(d.sp, sx)));
-    mac<false, false>(RB, sx, full(d.sm));
+    use_fstep<S, MODE>(st, cur);
   }
 }
 
@@ -567,70 +650,26 @@ __device__ __forceinline__ void factored_link(const Geom& g, const T* U, const T
   c.Ss = s8_stride(g);
   c.p = p;
   make_frame(g, mu, x, c.axis, c.nb);
-  const T cP = T(cf.c[0]), cR = T(cf.c[1]), cC = T(cf.c[2]);
-
-  su3<T> t;
-  double part;  // Re tr(U t) before the short-side rectangles and cubes are added
-  {
-    su3<T> tP, RA, RB;
-    set_zero(tP);
-    set_zero(RA);
-    set_zero(RB);
-    const LongSide<T> d0 = load_long<0>(c);
-    SYM_FENCE();
-    long_pipe<0>(c, tP, RA, RB, d0);
-    SYM_FENCE();
-    FCtx<T> lc = c;
-    launder(lc);
-    // links read as two rows here and below: the pass is bound by the bytes it loads
-    // (2.47 -> 2.41 ms FP32, 5.54 -> 5.35 ms FP64 on the 32^3 x 64 workload)
-    const su3<T> u = lc.template link_rows<0, 0, 0, 0, 0>();
-    su3<T> WR = mul<false, false>(lc.template link_rows<1, 0, 0, 0, 0>(), RA);  // U_{x+mu,mu} RA
-    mac<false, false>(WR, RB, lc.template link_rows<-1, 0, 0, 0, 0>());         // + RB U_{x-mu,mu}
-    a[0] = 18.0 - re_tr_mul(u, tP);
-    a[1] = 36.0 - re_tr_mul(u, WR);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      t.e[i].re = fma(cP, tP.e[i].re, cR * WR.e[i].re);
-      t.e[i].im = fma(cP, tP.e[i].im, cR * WR.e[i].im);
-    }
-    part = cf.c[0] * (18.0 - a[0]) + cf.c[1] * (36.0 - a[1]);  // Re tr(U t) so far
-  }
+  FState<T> st;
+  st.cP = T(cf.c[0]);
+  st.cR = T(cf.c[1]);
+  st.cC = T(cf.c[2]);
+  st.beta = cf.beta;
+  st.kick = kick;
+  st.out = out;
+  st.Vh = g.Vh;
+  st.mu = mu;
+  st.p = p;
+  st.cb = cb;
+  set_zero(st.tP);
+  set_zero(st.RA);
+  set_zero(st.RB);
+  const auto d0 = load_fstep<0>(c);
   SYM_FENCE();
-  {
-    // software-pipelined short-side rectangles and cube loops
-    su3<T> QA, QB;
-    const auto d0 = load_item<0>(c);
-    SYM_FENCE();
-    items_pipe<0>(c, t, QA, QB, d0, cR, cC);
-  }
-
-  FCtx<T> lc = c;
-  launder(lc);
-  const su3<T> u = lc.template link_rows<0, 0, 0, 0, 0>();
-  const su3<T> B = mul<false, false>(u, t);
-  a[2] = 18.0 * cf.c[1] + 72.0 * cf.c[2] - (re_tr(B) - part);
-  const su3<T> G = ta_scaled(B, T(cf.beta / 6.0));
-  cx<T>* dst = block_ptr(out, mu, p, g.Vh);
-  if constexpr (MODE == ForceOut::Store) {
-    store_link(dst, g.Vh, cb, G);
-  } else if constexpr (MODE == ForceOut::Grad) {
-    su3<T> gr = mul<false, false>(G, u);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      gr.e[e].re *= T(2);
-      gr.e[e].im *= T(2);
-    }
-    store_link(dst, g.Vh, cb, gr);
-  } else {
-    su3<T> q = load_link(static_cast<const cx<T>*>(dst), g.Vh, cb);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      q.e[e].re = T(double(q.e[e].re) - kick * double(G.e[e].re));
-      q.e[e].im = T(double(q.e[e].im) - kick * double(G.e[e].im));
-    }
-    store_link(dst, g.Vh, cb, q);
-  }
+  force_pipe<0, MODE>(c, st, d0);
+  a[0] = st.a[0];
+  a[1] = st.a[1];
+  a[2] = st.a[2];
 }
 
 }  // namespace factored
