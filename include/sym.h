@@ -283,7 +283,7 @@ int sym_set_coeffs_override(const double c[3]);
  * Process-wide choice of force algorithm: SYM_ALG_DIRECT multiplies out all 48
  * staples of each link (181 SU(3) products per link) and makes no assumption on the
  * matrices; SYM_ALG_FACTORED first forms the 6 plaquette staples of every link in the
- * workspace and builds rectangles and cube loops from them (63 products per link); it
+ * workspace and builds rectangles and cube loops from them (67.5 products per link); it
  * reads links and stores staples as two rows and rebuilds the third, which requires
  * the links to be special unitary to working precision, as the paper's link variables
  * are: for a link off SU(3) by delta (||U^dagger U - 1||), the rebuilt row differs from
