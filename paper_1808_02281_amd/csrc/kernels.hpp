@@ -39,9 +39,8 @@ hipError_t launch_force_direct(const Geom& g, const T* U, T* out, double kick, d
 // Factored force: plaquette staples first (one pass, one thread per site), then
 // rectangles and cube loops assembled from them (second pass, one thread per link).
 // Staple buffer: 8 slots of 6 complex (two rows) per link (two slots unused), see
-// force_factored.hip.
-// Its element planes are kS8Pad complex numbers longer than V/2 so that the 576 planes
-// do not all start at the same power-of-two alignment.
+// factored.hpp. Each element plane holds V/2 + kS8Pad complex numbers (no padding at
+// present; the constant is kept so that the plane stride has one definition).
 constexpr int kS8Pad = 0;
 __host__ __device__ inline int s8_stride(const Geom& g) { return g.Vh + kS8Pad; }
 // Links per workgroup of the factored force pass: 128 (FP32) and 64 (FP64). At one or two
