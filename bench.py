@@ -27,7 +27,7 @@ METRIC = "link-forces/sec + % HBM/VALU roofline, Symanzik force 32^3x64, FP32 vs
 WORKLOAD = "thermal_32x32x32x64"
 
 # Work per link-force (flop; FMA = 2; SU(3) product 198, product accumulated into a
-# matrix 216). See the design notes for the derivation.
+# matrix 216), each figure stated beside its constant.
 FLOP_PAPER = 36770          # the paper's algorithm: 180 staple products, sums, U t, TA
 FLOP_STAPLES = 2079         # factored pass 1: 42 products per site (10.5 per link)
 FLOP_FACTORED = 12909       # factored pass 2: 57 products, 55 accumulations, weights, traces, TA
@@ -39,7 +39,7 @@ BYTES_DIRECT = lambda r: (18 + 18) * r                   # read U, write G
 
 # Fat-link path force (asqtad/HISQ smearing), flop per link of each kernel, counted from
 # the kernel source: SU(3) product 198, product accumulated into a matrix 216, matrix
-# axpy 36, matrix scaling or addition 18 (see the design notes for the breakdown).
+# axpy 36, matrix scaling or addition 18.
 FAT_FLOP = {"fat_fk1": 2754, "fat_fk2": 7722, "fat_fk3": 2916, "fat_bk3": 2538, "fat_bk2": 8010,
             "fat_gk": 23418}
 # minimum HBM matrices (18 reals) read + written per link by each kernel
@@ -506,7 +506,7 @@ def fma_rate(torch, dtype, iters=8192, reps=5):
 
 def measured_peaks(sym, torch):
     """Device rates the roofline fractions can be read against: vector FMA throughput
-    (the probe kernel, this build's non-packed FP32 and FP64 FMAs) and HBM bandwidth of a
+    (the probe kernel: non-packed FP32 and FP64 FMAs, as the library's kernels are compiled) and HBM bandwidth of a
     plain 2 GiB device copy (read + write) and fill (write), best of 5."""
     res = {"fp32_fma_tflops": fma_rate(torch, torch.float32), "fp64_fma_tflops": fma_rate(torch, torch.float64)}
     n = 1 << 29  # 2 GiB of float32
@@ -554,8 +554,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the force would shard by domain decomposition; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the force would shard by domain decomposition along t, exchanging two t-slices of links "
+              "per side).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

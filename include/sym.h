@@ -57,7 +57,7 @@ typedef enum {
   SYM_ENULL = -2,        /* a required pointer is NULL */
   SYM_EWORKSPACE = -3,   /* ws_bytes < sym_workspace_bytes(L, prec) */
   SYM_EHIP = -4,         /* a HIP launch failed (e.g. no gfx950 device) */
-  SYM_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  SYM_EUNSUPPORTED = -5  /* valid request this library does not implement */
 } sym_status;
 
 typedef enum { SYM_F32 = 1, SYM_F64 = 2 } sym_prec;

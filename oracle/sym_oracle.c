@@ -28,7 +28,7 @@
  *     share only the loop walk and are checked against each other. This file returns
  *     G = (beta/6)(U t)_TA, the antihermitian matrix; the paper's Hermitian force is iG.
  *
- * Parity-relevant readings of the paper (listed with the rest in the design notes):
+ * Parity-relevant readings of the paper:
  *   - U_{n,mu} lives on the link (n, n+mu) (the paper's text has a typo there);
  *   - the factor i of the force sits outside the TA projection;
  *   - all four directions are periodic; mu = 0..3 is x,y,z,t; x runs fastest;

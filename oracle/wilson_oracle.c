@@ -26,7 +26,7 @@
  * the convention of the gauge force G of Sec. II. By eq. 18_6_24_0 the pseudofermion
  * action at fixed X, Y changes by -dPsi, so its force in that convention is -G.
  *
- * Readings (listed with the rest in the design notes): gamma matrices are Hermitian
+ * Readings: gamma matrices are Hermitian
  * in the DeGrand-Rossi basis, gamma_1..gamma_4 for the x, y, z, t directions; the
  * paper's leaf products U_{n;mu,nu} are plaquettes starting at n (first step mu,
  * second nu); spinors are AoS (Lt,Lz,Ly,Lx,4,3): site, spin, colour.

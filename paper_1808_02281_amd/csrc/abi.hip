@@ -967,7 +967,7 @@ const char* sym_strerror(int status) {
     case SYM_ENULL: return "required pointer is NULL";
     case SYM_EWORKSPACE: return "workspace smaller than sym_workspace_bytes()";
     case SYM_EHIP: return "HIP launch failed";
-    case SYM_EUNSUPPORTED: return "not supported by this build";
+    case SYM_EUNSUPPORTED: return "not supported by this library";
     default: return "unknown status";
   }
 }

@@ -1,7 +1,7 @@
 """The FMA-rate probe that the bench quotes measured peaks from (libsymprobe.so, a
 benchmark helper outside the libsym ABI): it runs, its output is finite, and the rate it
 implies lies below the data-sheet vector peak of the precision (FP32 157.3 TFLOP/s
-counting packed FMA, which this build does not emit; FP64 78.6)."""
+counting packed FMA, which the library is compiled not to emit; FP64 78.6)."""
 import pytest
 import torch
 
