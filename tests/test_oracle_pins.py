@@ -289,6 +289,30 @@ def test_force_links_equals_full_force(coeffs, L):
     assert np.abs(G).max() > 0.1
 
 
+def test_scatter_force_does_not_depend_on_the_thread_count(coeffs):
+    """The scatter orders every link's deposits by t-slice phase, so the whole-field
+    force (and the fat-link gradient) is bitwise the same on one thread and on many."""
+    L = (4, 4, 4, 8)
+    U = gaugegen.haar_links(L, 3)
+    Lf = (4, 4, 4, 10)  # the fat paths reach two steps back and forth: phases of 5 slices
+    Uf = gaugegen.haar_links(Lf, 4)
+    rng = np.random.default_rng(5)
+    GV = rng.standard_normal(Uf.shape) + 1j * rng.standard_normal(Uf.shape)
+    GW = rng.standard_normal(Uf.shape) + 1j * rng.standard_normal(Uf.shape)
+    cf = (0.61, -0.071, 0.013, -0.0029, -0.055, -0.043)
+    before = oracle.set_num_threads(0)
+    out = []
+    try:
+        for n in (1, max(2, before)):
+            oracle.set_num_threads(n)
+            out.append((oracle.force(U, L, coeffs, BETA), oracle.staple_sums(U, L),
+                        oracle.fat_grad(Uf, Lf, cf, GV, GW)))
+    finally:
+        oracle.set_num_threads(before)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 # ---------------------------------------------------------------- exponential map
 
 def test_su3_exp_against_eigendecomposition():
