@@ -257,6 +257,23 @@ def test_parity_32x32x32x64_every_link(sym, c, big_field, big_oracle, prec):
         assert se2e <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_force_bitwise_repeatable_32x32x32x64(sym, big_field, prec):
+    """Twenty force calls with the fused action on the benchmark workload give bitwise the
+    same forces and action as the first: nothing in the passes depends on timing (each
+    thread writes only its own staples and force, the reductions have a fixed order)."""
+    print(f"case thermal_32x32x32x64 {prec} repeatability", flush=True)
+    sym.set_force_algorithm("auto")
+    L, U = big_field
+    Us = to_soa(sym, U, L, prec, device())
+    F0, S0 = sym.force(Us, L, U0, BETA, with_action=True)
+    F = torch.empty_like(F0)
+    for _ in range(20):
+        _, S = sym.force(Us, L, U0, BETA, with_action=True, out=F)
+        assert torch.equal(F, F0)
+        assert torch.equal(S, S0)
+
+
 # ------------------------------------------- fused action with c_cube = 0
 
 @pytest.mark.parametrize("alg", ["direct", "factored"])
