@@ -140,7 +140,10 @@ int sym_action_grad(const int32_t L[4], double u0, double beta, int prec, const 
  * projected onto SU(3) in double (Gram-Schmidt of the first two rows, third row their
  * conjugate cross product) before it is rounded to float, so the unitarity defect stays
  * at float rounding (about 1e-7) however many steps are taken; the projection moves a
- * link by its defect, far below the FP32 force tolerance.
+ * link by its defect, far below the FP32 force tolerance. The call returns before the
+ * trajectory runs, so it cannot return a status for a trajectory that diverges (dt too
+ * large): H then comes back non-finite or with a large H after - H before, and
+ * sym_check_links counts the non-finite link elements; callers check either.
  */
 int md_leapfrog(const int32_t L[4], double u0, double beta, int prec, void* U, void* P, double dt, int32_t nsteps,
                 double* H_dev, void* ws, size_t ws_bytes, sym_stream_t stream);
