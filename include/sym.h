@@ -271,6 +271,18 @@ int sym_unpack_spinor(const int32_t L[4], int prec, const void* soa, void* aos_l
 int sym_check_links(const int32_t L[4], int prec, const void* U, double* out_dev, void* ws, size_t ws_bytes,
                     sym_stream_t stream);
 
+/*
+ * Link-field repair for the same precondition: every link of U (in place) is replaced by
+ * its projection onto SU(3), computed in double: the first row normalised, the second
+ * orthogonalised against it (Gram-Schmidt) and normalised, the third set to the complex
+ * conjugate of the cross product of the first two (det = 1), then rounded to the field's
+ * precision. A link within rounding of SU(3) moves by its unitarity defect; a link with a
+ * zero-norm row or a non-finite element comes out non-finite (sym_check_links counts
+ * it). For fields that come from elsewhere (files, other codes); md_leapfrog keeps its own
+ * links in SU(3). No workspace.
+ */
+int sym_reunitarise(const int32_t L[4], int prec, void* U, sym_stream_t stream);
+
 /* Canonical (Lt,Lz,Ly,Lx,4,3,3) complex array -> SoA even-odd layout, and back. */
 int sym_pack(const int32_t L[4], int prec, const void* aos_lex, void* soa, sym_stream_t stream);
 int sym_unpack(const int32_t L[4], int prec, const void* soa, void* aos_lex, sym_stream_t stream);
@@ -292,8 +304,8 @@ int sym_set_coeffs_override(const double c[3]);
  * are: for a link off SU(3) by delta (||U^dagger U - 1||), the rebuilt row differs from
  * the stored one by O(delta), and so does the force. md_leapfrog keeps its links within
  * float rounding of SU(3) in SYM_F32 and within double rounding in SYM_F64; fields
- * from elsewhere can be checked with sym_check_links. SYM_ALG_AUTO (default) is
- * SYM_ALG_FACTORED. SYM_EINVAL for other values.
+ * from elsewhere can be checked with sym_check_links and repaired with sym_reunitarise.
+ * SYM_ALG_AUTO (default) is SYM_ALG_FACTORED. SYM_EINVAL for other values.
  */
 int sym_set_force_algorithm(int algorithm);
 

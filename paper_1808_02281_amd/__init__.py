@@ -27,6 +27,7 @@ from .api import (  # noqa: F401
     profile_enable,
     prec_of,
     release_workspaces,
+    reunitarise,
     set_coeffs_override,
     set_force_algorithm,
     unpack,

@@ -42,6 +42,7 @@ EXPORTS = (
     "sym_pack_spinor",
     "sym_unpack_spinor",
     "sym_check_links",
+    "sym_reunitarise",
 )
 FAT_MODES = {"grad": 0, "force": 1}
 FAT_REUSE_LINKS = 2
@@ -123,6 +124,8 @@ def lib():
     L.sym_unpack_spinor.restype = ctypes.c_int
     L.sym_check_links.argtypes = [i32p, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     L.sym_check_links.restype = ctypes.c_int
+    L.sym_reunitarise.argtypes = [i32p, ctypes.c_int, vp, vp]
+    L.sym_reunitarise.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -171,6 +171,14 @@ def check_links(U, L):
     return out
 
 
+def reunitarise(U, L):
+    """Project every link of U onto SU(3) in place (sym_reunitarise); returns U."""
+    _check_field("U", U, L)
+    _lib.check("sym_reunitarise", _lib.lib().sym_reunitarise(_lib.dims(L), prec_of(U.dtype), _ptr(U),
+                                                             _stream(U.device)))
+    return U
+
+
 def set_coeffs_override(c):
     """Use loop coefficients c = (c_plaq, c_rect, c_cube) instead of u0's; None restores."""
     if c is None:

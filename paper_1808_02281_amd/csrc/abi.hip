@@ -13,6 +13,7 @@
 
 #include "../../include/sym.h"
 #include "fat.hpp"
+#include "project.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -754,6 +755,18 @@ int sym_check_links(const int32_t L[4], int prec, const void* U, double* out_dev
   const hipError_t e = timed("check_links", s, [&] {
     return prec == SYM_F64 ? sym::launch_check_links<double>(g, static_cast<const double*>(U), w.act, out_dev, s)
                            : sym::launch_check_links<float>(g, static_cast<const float*>(U), w.act, out_dev, s);
+  });
+  return hip_status(e);
+}
+
+int sym_reunitarise(const int32_t L[4], int prec, void* U, sym_stream_t stream) {
+  Geom g;
+  int rc;
+  if ((rc = make_geom(L, &g)) || (rc = check_prec(prec)) || (rc = check_ptr(U))) return rc;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const hipError_t e = timed("reunitarise", s, [&] {
+    return prec == SYM_F64 ? sym::launch_reunitarise<double>(g, static_cast<double*>(U), s)
+                           : sym::launch_reunitarise<float>(g, static_cast<float*>(U), s);
   });
   return hip_status(e);
 }

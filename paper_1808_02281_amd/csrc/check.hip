@@ -2,8 +2,8 @@
 // first two rows and rebuilds the third, so it assumes special-unitary links: per link
 // the unitarity defect ||U^dagger U - 1||_F and |det U - 1| in double, and whether any
 // element is not finite. Per-workgroup maxima (order-independent, hence deterministic)
-// and counts, then one finishing block.
-#include "kernels.hpp"
+// and counts, then one finishing block. And the repair: every link projected onto SU(3).
+#include "project.hpp"
 
 namespace sym {
 namespace {
@@ -89,7 +89,34 @@ __global__ __launch_bounds__(kBlock) void check_finish_kernel(const double* __re
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reunitarise_kernel(Geom g, T* __restrict__ U, int ntiles) {
+  const LinkTile lt = link_tile(g, blockIdx.x, ntiles);
+  const int cb = lt.chunk * kBlock + threadIdx.x;
+  if (cb >= g.Vh) return;
+  cx<T>* blk = block_ptr(U, lt.mu, lt.p, g.Vh);
+  const su3<T> u = load_link(static_cast<const cx<T>*>(blk), g.Vh, cb);
+  su3<double> d;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d.e[i] = cd{double(u.e[i].re), double(u.e[i].im)};
+  proj::project_su3(d);
+  su3<T> out;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out.e[i] = cx<T>{T(d.e[i].re), T(d.e[i].im)};
+  store_link(blk, g.Vh, cb, out);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_reunitarise(const Geom& g, T* U, hipStream_t s) {
+  const int nt = link_tiles(g);
+  reunitarise_kernel<T><<<nt, kBlock, 0, s>>>(g, U, nt);
+  return hipGetLastError();
+}
+
+template hipError_t launch_reunitarise<float>(const Geom&, float*, hipStream_t);
+template hipError_t launch_reunitarise<double>(const Geom&, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_check_links(const Geom& g, const T* U, double* partials, double* out, hipStream_t s) {

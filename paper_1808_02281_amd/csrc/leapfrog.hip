@@ -4,7 +4,7 @@
 // antihermitian Pi = i p_a T_a, the equation of motion of U is U-dot = Pi U, and the
 // kinetic energy is -tr(Pi^2) = (1/2) sum_a p_a^2 per link. All of it in double; in
 // the FP32 layout the updated link is projected onto SU(3) and rounded to float on store.
-#include "kernels.hpp"
+#include "project.hpp"
 
 namespace sym {
 namespace {
@@ -88,37 +88,6 @@ __device__ __forceinline__ su3<double> to_double(const su3<T>& a) {
   return r;
 }
 
-// Nearest-by-rows special-unitary matrix: normalise the first row, orthogonalise the
-// second against it (Gram-Schmidt) and normalise it, and set the third row to the complex
-// conjugate of the cross product of the first two (det = 1). For a matrix within rounding
-// of SU(3) it moves each element by the size of its unitarity defect.
-__device__ __forceinline__ void project_su3(su3<double>& u) {
-  double n0 = 0.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) n0 += u.e[j].re * u.e[j].re + u.e[j].im * u.e[j].im;
-  const double r0 = 1.0 / sqrt(n0);
-#pragma unroll
-  for (int j = 0; j < 3; ++j) u.e[j] = cscale(u.e[j], r0);
-  cd ov{0.0, 0.0};  // <row0, row1> = sum conj(row0_j) row1_j
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    ov.re += u.e[j].re * u.e[3 + j].re + u.e[j].im * u.e[3 + j].im;
-    ov.im += u.e[j].re * u.e[3 + j].im - u.e[j].im * u.e[3 + j].re;
-  }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const cd t = cmul(ov, u.e[j]);
-    u.e[3 + j] = cd{u.e[3 + j].re - t.re, u.e[3 + j].im - t.im};
-  }
-  double n1 = 0.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) n1 += u.e[3 + j].re * u.e[3 + j].re + u.e[3 + j].im * u.e[3 + j].im;
-  const double r1 = 1.0 / sqrt(n1);
-#pragma unroll
-  for (int j = 0; j < 3; ++j) u.e[3 + j] = cscale(u.e[3 + j], r1);
-  complete_third_row(u);
-}
-
 // U <- exp(dt Pi) U in double. In the FP32 layout the product is projected back onto
 // SU(3) before it is rounded to float: rounding leaves a unitarity defect of a few
 // 1e-8 per step, which would otherwise accumulate over a trajectory, while the force
@@ -139,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Geom g, T* __restrict__ U
   cx<T>* ub = block_ptr(U, mu, p, g.Vh);
   const su3<double> u = to_double(load_link(static_cast<const cx<T>*>(ub), g.Vh, cb));
   su3<double> un = mul<false, false>(E, u);
-  if constexpr (sizeof(T) == 4) project_su3(un);
+  if constexpr (sizeof(T) == 4) proj::project_su3(un);
   su3<T> out;
 #pragma unroll
   for (int i = 0; i < 9; ++i) out.e[i] = cx<T>{T(un.e[i].re), T(un.e[i].im)};

@@ -149,6 +149,16 @@ def test_check_links_validation(L_):
     assert c(ok, 1, FAKE, _at(FAKE, 32), FAKE3, HUGE, None) == -1
 
 
+def test_reunitarise_validation(L_):
+    ok = _dims(4, 4, 4, 4)
+    r = L_.sym_reunitarise
+    assert r(_dims(4, 4, 4, 5), 1, FAKE, None) == -1
+    assert r(_dims(4, 4, 2, 4), 2, FAKE, None) == -1
+    assert r(ok, 3, FAKE, None) == -1
+    assert r(ok, 1, None, None) == -2
+    assert r(ok, 2, _at(FAKE, 8), None) == -1  # misaligned
+
+
 def test_layout_and_switch_validation(L_):
     assert L_.sym_pack(_dims(4, 4, 4, 5), 1, FAKE, FAKE, None) == -1
     assert L_.sym_pack(_dims(4, 4, 4, 4), 1, None, FAKE, None) == -2

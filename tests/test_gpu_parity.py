@@ -328,3 +328,44 @@ def test_check_links(sym):
     assert abs(out[0] - (1.01 ** 2 - 1) * np.sqrt(3)) <= 1e-12
     assert abs(out[1] - (1.01 ** 3 - 1)) <= 1e-12
     assert out[2] == 2
+
+
+def _project_rows(M):
+    """SU(3) projection by rows (numpy, double): row 0 normalised, row 1 orthogonalised
+    against it and normalised, row 2 = conj(row 0 x row 1)."""
+    r0 = M[..., 0, :] / np.linalg.norm(M[..., 0, :], axis=-1, keepdims=True)
+    r1 = M[..., 1, :] - np.sum(np.conj(r0) * M[..., 1, :], axis=-1, keepdims=True) * r0
+    r1 = r1 / np.linalg.norm(r1, axis=-1, keepdims=True)
+    return np.stack([r0, r1, np.conj(np.cross(r0, r1))], axis=-2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_reunitarise(sym, prec):
+    """sym_reunitarise against the projection written out in numpy, on links pulled off
+    SU(3) by complex noise; SU(3) links barely move; the result passes sym_check_links;
+    a link with a non-finite element stays non-finite and is counted."""
+    L = (4, 6, 4, 6)
+    dev = device()
+    rng = np.random.default_rng(17)
+    U = gaugegen.haar_links(L, 13)
+    V = U + 0.05 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    V = rounded(V, prec)
+    want = _project_rows(V)
+    Vs = to_soa(sym, V, L, prec, dev)
+    got = from_soa(sym, sym.reunitarise(Vs, L), L)
+    tol = 1e-14 if prec == "f64" else 4e-7
+    assert np.abs(got - want).max() <= tol
+    chk = sym.check_links(Vs, L).cpu().numpy()
+    assert chk[0] <= (1e-14 if prec == "f64" else 2e-6) and chk[1] <= (1e-14 if prec == "f64" else 2e-6)
+    assert chk[2] == 0
+    # special-unitary links move by their defect only
+    Us = to_soa(sym, rounded(U, prec), L, prec, dev)
+    before = from_soa(sym, Us, L)
+    after = from_soa(sym, sym.reunitarise(Us, L), L)
+    assert np.abs(after - before).max() <= (1e-15 if prec == "f64" else 4e-7)
+    # non-finite input stays non-finite
+    W = rounded(U, prec).copy()
+    W[1, 2, 3, 0, 2, 1, 1] = np.nan
+    Ws = to_soa(sym, W, L, prec, dev)
+    sym.reunitarise(Ws, L)
+    assert sym.check_links(Ws, L).cpu().numpy()[2] == 1
