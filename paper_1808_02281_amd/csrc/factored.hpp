@@ -122,25 +122,11 @@ struct FCtx {
   int axis[4];
   Nbr nb;
 
-  // U_{x+d, axis[AX]} (forward link)
+  // the first two rows of U_{x+d, axis[AX]} (a third less link traffic than all nine
+  // elements), loaded only: full() rebuilds the third where the link is used, so that the
+  // loads can be issued ahead of their use like the staples'
   template <int D0, int D1, int D2, int D3, int AX>
-  __device__ __forceinline__ su3<T> link() const {
-    constexpr int dp = offset_parity<D0, D1, D2, D3>();
-    return load_link(block_ptr(U, axis[AX], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
-  }
-
-  // U_{x+d, axis[AX]} from its first two rows, the third rebuilt (special unitary):
-  // a third less link traffic than load_link
-  template <int D0, int D1, int D2, int D3, int AX>
-  __device__ __forceinline__ su3<T> link_rows() const {
-    constexpr int dp = offset_parity<D0, D1, D2, D3>();
-    return load_su3_rows(block_ptr(U, axis[AX], p ^ dp, Vh), Vh, nbr_cb<D0, D1, D2, D3>(nb));
-  }
-
-  // the first two rows of U_{x+d, axis[AX]}, loaded only (rebuilt where used, so that
-  // the loads can be issued ahead of their use like the staples')
-  template <int D0, int D1, int D2, int D3, int AX>
-  __device__ __forceinline__ Rows2<T> link_rows2() const {
+  __device__ __forceinline__ Rows2<T> link_rows() const {
     constexpr int dp = offset_parity<D0, D1, D2, D3>();
     const cx<T>* blk = block_ptr(U, axis[AX], p ^ dp, Vh);
     const unsigned bytes = 6u * (unsigned)Vh * (unsigned)sizeof(cx<T>);
@@ -191,12 +177,6 @@ struct FCtx {
       }
     }
     return u;
-  }
-
-  // S(x+d, axis[AX], e) for e = sign ES along frame axis EAX
-  template <int D0, int D1, int D2, int D3, int AX, int EAX, int ES>
-  __device__ __forceinline__ su3<T> stap() const {
-    return full(stap_rows<D0, D1, D2, D3, AX, EAX, ES>());
   }
 };
 
@@ -505,9 +485,9 @@ __device__ __forceinline__ auto load_fstep(const FCtx<T>& c0) {
     return d;
   } else if constexpr (S == 6) {
     Middle<T> d;
-    d.u = c.template link_rows2<0, 0, 0, 0, 0>();
-    d.up = c.template link_rows2<1, 0, 0, 0, 0>();
-    d.um = c.template link_rows2<-1, 0, 0, 0, 0>();
+    d.u = c.template link_rows<0, 0, 0, 0, 0>();
+    d.up = c.template link_rows<1, 0, 0, 0, 0>();
+    d.um = c.template link_rows<-1, 0, 0, 0, 0>();
     return d;
   } else if constexpr (S < kSteps - 1) {
     constexpr int K = S - 7, F = K / 3, k = K % 3;
@@ -526,17 +506,17 @@ __device__ __forceinline__ auto load_fstep(const FCtx<T>& c0) {
       Short<T> d;
       d.see = c.template stap_rows<0, f1, f2, f3, 0, fa, fs>();
       if constexpr (fs > 0) {
-        d.lnk = c.template link_rows2<0, 0, 0, 0, fa>();
-        d.uxm = c.template link_rows2<1, 0, 0, 0, fa>();
+        d.lnk = c.template link_rows<0, 0, 0, 0, fa>();
+        d.uxm = c.template link_rows<1, 0, 0, 0, fa>();
       } else {
-        d.lnk = c.template link_rows2<0, f1, f2, f3, fa>();
-        d.uxm = c.template link_rows2<1, f1, f2, f3, fa>();
+        d.lnk = c.template link_rows<0, f1, f2, f3, fa>();
+        d.uxm = c.template link_rows<1, f1, f2, f3, fa>();
       }
       return d;
     }
   } else {
     Last<T> d;
-    d.u = c.template link_rows2<0, 0, 0, 0, 0>();
+    d.u = c.template link_rows<0, 0, 0, 0, 0>();
     return d;
   }
 }
